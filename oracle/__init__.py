@@ -1,0 +1,225 @@
+"""Plain FP64 CPU oracle for LPA + ICI HDR reconstruction (arXiv 1308.4908).
+
+TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  This module marshals numpy arrays
+into the C oracle (``lpa_oracle.c``); every step of the method is computed
+there, in FP64, single-threaded.  It shares no code with the GPU library.
+
+Rig and parameter descriptions are plain dicts (see ``synth.rig``):
+sensor keys  width, height, cfa, affine(6), exposure, gain, read_sigma,
+             black_level, saturation
+param keys   out_w, out_h, out_affine(6), order, radii, h (optional), gamma,
+             green_ratio, tau_inv
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lpa_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liblpa_oracle.so")
+_lib = None
+
+CFA = {"RGGB": 0, "BGGR": 1, "GRBG": 2, "GBRG": 3}
+MAX_SCALES = 8
+
+
+class _Sensor(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("cfa", ctypes.c_int32),
+        ("affine", ctypes.c_double * 6),
+        ("exposure", ctypes.c_double),
+        ("gain", ctypes.c_double),
+        ("read_sigma", ctypes.c_double),
+        ("black_level", ctypes.c_double),
+        ("saturation", ctypes.c_double),
+    ]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("out_w", ctypes.c_int32),
+        ("out_h", ctypes.c_int32),
+        ("out_affine", ctypes.c_double * 6),
+        ("order", ctypes.c_int32),
+        ("n_scales", ctypes.c_int32),
+        ("radii", ctypes.c_double * MAX_SCALES),
+        ("h", ctypes.c_double * MAX_SCALES),
+        ("gamma", ctypes.c_double),
+        ("green_ratio", ctypes.c_double),
+        ("tau_inv", ctypes.c_double),
+        ("exhaustive", ctypes.c_int32),
+    ]
+
+
+class _Fit(ctypes.Structure):
+    _fields_ = [
+        ("yhat", ctypes.c_double),
+        ("var", ctypes.c_double),
+        ("rho", ctypes.c_double),
+        ("c1x", ctypes.c_double),
+        ("c1y", ctypes.c_double),
+        ("n", ctypes.c_int32),
+        ("valid", ctypes.c_int32),
+    ]
+
+
+FIT_DTYPE = np.dtype(
+    [("yhat", "f8"), ("var", "f8"), ("rho", "f8"), ("c1x", "f8"), ("c1y", "f8"),
+     ("n", "i4"), ("valid", "i4")],
+    align=True,
+)
+assert FIT_DTYPE.itemsize == ctypes.sizeof(_Fit)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (strict IEEE FP64: no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.run(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-Wall",
+             "-Wextra", "-o", tmp, _SRC, "-lm"],
+            check=True,
+        )
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.orc_reconstruct.restype = ctypes.c_int
+        lib.orc_reconstruct.argtypes = [
+            ctypes.POINTER(_Sensor), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+            ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ]
+        lib.orc_sample_radiance.restype = ctypes.c_int
+        lib.orc_sample_radiance.argtypes = [
+            ctypes.POINTER(_Sensor), ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+            ctypes.POINTER(ctypes.c_double),
+        ]
+        lib.orc_cfa_channel.restype = ctypes.c_int
+        lib.orc_cfa_channel.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        lib.orc_ici_select.restype = ctypes.c_int
+        lib.orc_ici_select.argtypes = [
+            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+            ctypes.POINTER(ctypes.c_double),
+        ]
+        _lib = lib
+    return _lib
+
+
+def _sensor_struct(d: dict) -> _Sensor:
+    s = _Sensor()
+    s.width = int(d["width"])
+    s.height = int(d["height"])
+    cfa = d.get("cfa", "RGGB")
+    s.cfa = CFA[cfa] if isinstance(cfa, str) else int(cfa)
+    for i, a in enumerate(d["affine"]):
+        s.affine[i] = float(a)
+    s.exposure = float(d["exposure"])
+    s.gain = float(d["gain"])
+    s.read_sigma = float(d["read_sigma"])
+    s.black_level = float(d["black_level"])
+    s.saturation = float(d["saturation"])
+    return s
+
+
+def _params_struct(p: dict, exhaustive: bool) -> _Params:
+    q = _Params()
+    q.out_w = int(p["out_w"])
+    q.out_h = int(p["out_h"])
+    for i, a in enumerate(p["out_affine"]):
+        q.out_affine[i] = float(a)
+    q.order = int(p["order"])
+    radii = list(p["radii"])
+    q.n_scales = len(radii)
+    hs = list(p.get("h") or [0.0] * len(radii))
+    for i, r in enumerate(radii):
+        q.radii[i] = float(r)
+        q.h[i] = float(hs[i])
+    q.gamma = float(p.get("gamma", 2.0))
+    q.green_ratio = float(p.get("green_ratio", 1.0))
+    q.tau_inv = float(p.get("tau_inv", 1e-5))
+    q.exhaustive = 1 if exhaustive else 0
+    return q
+
+
+def reconstruct(sensors, raws, params, pixels=None, want_fits=False, exhaustive=False):
+    """Run the oracle.
+
+    sensors : list of sensor dicts; raws : list of 2-D arrays (DN values, any
+    numeric dtype; converted exactly to float64); params : parameter dict;
+    pixels : optional (n, 2) int array of (u, v) output pixels (default: the
+    whole grid, row-major).  Returns a dict with ``rgb`` (n, 3) float64,
+    ``scale_map`` (n, 3) uint8, ``margin`` (n, 3) and, if asked, ``fits``
+    (n, 3, n_scales, 3) structured array (see FIT_DTYPE).
+    """
+    lib = _load()
+    ns = len(sensors)
+    sens = (_Sensor * ns)(*[_sensor_struct(d) for d in sensors])
+    planes = [np.ascontiguousarray(np.asarray(r), dtype=np.float64) for r in raws]
+    for d, pl in zip(sensors, planes):
+        if pl.shape != (int(d["height"]), int(d["width"])):
+            raise ValueError(f"raw plane shape {pl.shape} does not match sensor {d['height']}x{d['width']}")
+    ptrs = (ctypes.c_void_p * ns)(*[pl.ctypes.data for pl in planes])
+    prm = _params_struct(params, exhaustive)
+    if pixels is None:
+        n = prm.out_w * prm.out_h
+        pix_ptr = None
+        pix = None
+    else:
+        pix = np.ascontiguousarray(np.asarray(pixels, dtype=np.int32).reshape(-1, 2))
+        n = pix.shape[0]
+        pix_ptr = pix.ctypes.data
+    rgb = np.empty((n, 3), np.float64)
+    smap = np.empty((n, 3), np.uint8)
+    margin = np.empty((n, 3), np.float64)
+    fits = np.zeros((n, 3, prm.n_scales, 3), FIT_DTYPE) if want_fits else None
+    rc = lib.orc_reconstruct(
+        sens, ns, ptrs, ctypes.byref(prm), pix_ptr, n, rgb.ctypes.data, smap.ctypes.data,
+        margin.ctypes.data, fits.ctypes.data if fits is not None else None,
+    )
+    if rc != 0:
+        raise ValueError(f"oracle rejected its arguments (code {rc})")
+    out = {"rgb": rgb, "scale_map": smap, "margin": margin}
+    if fits is not None:
+        out["fits"] = fits
+    return out
+
+
+def sample_radiance(sensor: dict, y: float):
+    """(usable, f_hat, var_hat) of one digital value y on a sensor."""
+    lib = _load()
+    s = _sensor_struct(sensor)
+    f = ctypes.c_double()
+    v = ctypes.c_double()
+    ok = lib.orc_sample_radiance(ctypes.byref(s), float(y), ctypes.byref(f), ctypes.byref(v))
+    return bool(ok), f.value, v.value
+
+
+def cfa_channel(cfa, x: int, y: int) -> int:
+    lib = _load()
+    return lib.orc_cfa_channel(CFA[cfa] if isinstance(cfa, str) else int(cfa), int(x), int(y))
+
+
+def ici_select(yhat, var, valid, gamma: float = 2.0):
+    """The ICI rule on given per-scale estimates: (chosen index or -1, margin)."""
+    lib = _load()
+    y = np.ascontiguousarray(yhat, np.float64)
+    v = np.ascontiguousarray(var, np.float64)
+    ok = np.ascontiguousarray(valid, np.int32)
+    mu = ctypes.c_double()
+    k = lib.orc_ici_select(len(y), y.ctypes.data, v.ctypes.data, ok.ctypes.data, float(gamma),
+                           ctypes.byref(mu))
+    return k, mu.value
