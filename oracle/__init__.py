@@ -22,6 +22,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lpa_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liblpa_oracle.so")
+# A test that checks the pins catch planted mistakes points this at a mutated build.
+_OVERRIDE = os.environ.get("LPA_ORACLE_LIB_OVERRIDE")
 _lib = None
 
 CFA = {"RGGB": 0, "BGGR": 1, "GRBG": 2, "GBRG": 3}
@@ -94,9 +96,12 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-            build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        if _OVERRIDE:
+            lib = ctypes.CDLL(_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+                build()
+            lib = ctypes.CDLL(_LIB_PATH)
         lib.orc_reconstruct.restype = ctypes.c_int
         lib.orc_reconstruct.argtypes = [
             ctypes.POINTER(_Sensor), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),

@@ -1,0 +1,68 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a private copy of the oracle source (on the
+CPU, never on a GPU), builds it, and runs the pin suite against that build in a
+subprocess; the suite must fail.  A mistake the pins did not catch would make
+them too weak to trust the oracle.
+"""
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lpa_oracle.c")
+
+# (name, original text, planted mistake)
+MUTATIONS = [
+    ("window not truncated", "const double k = exp(-d2 / h) - k_edge;", "const double k = exp(-d2 / h);"),
+    ("window exp(-d2/h^2)", "const double k = exp(-d2 / h) - k_edge;", "const double k = exp(-d2 / (h * h)) - exp(-r * r / (h * h));"),
+    ("weight 1/sigma", "orc_sample smp = {dx, dy, f, 1.0 / var, k};", "orc_sample smp = {dx, dy, f, 1.0 / sqrt(var), k};"),
+    ("B without K^2", "const double w2 = s->k * s->k * s->ivar;", "const double w2 = s->k * s->ivar;"),
+    ("basis dx*dy -> dx*dx", "phi[4] = dx * dy;", "phi[4] = dx * dx;"),
+    ("offset sign", "const double dx = Xk - X, dy = Yk - Y;", "const double dx = X - Xk, dy = Yk - Y;"),
+    ("affine transposed", "*X = a[0] * x + a[1] * y + a[2];", "*X = a[0] * x + a[3] * y + a[2];"),
+    ("radiance without exposure", "const double f = (y - s->black_level) / (g * e);",
+     "const double f = (y - s->black_level) / g;"),
+    ("variance gain not squared", "*var_hat = (g * g * e * shot + s->read_sigma * s->read_sigma) / (g * g * e * e);",
+     "*var_hat = (g * e * shot + s->read_sigma * s->read_sigma) / (g * g * e * e);"),
+    ("variance without readout", "*var_hat = (g * g * e * shot + s->read_sigma * s->read_sigma) / (g * g * e * e);",
+     "*var_hat = (g * g * e * shot + 1e-30) / (g * g * e * e);"),
+    ("saturation exclusive", "if (y >= s->saturation) return 0;", "if (y > s->saturation) return 0;"),
+    ("ICI strict tie", "if (lo_run <= hi_run)", "if (lo_run < hi_run)"),
+    ("no equilibration", "At[i][j] = scale[i] * A[i][j] * scale[j];", "At[i][j] = A[i][j];"),
+    ("back substitution index", "for (int k = i + 1; k < n; ++k) t -= L[k][i] * x[k];",
+     "for (int k = i + 1; k < n; ++k) t -= L[i][k] * x[k];"),
+    ("box too small", "const double wx = r * sqrt(i00 * i00 + i01 * i01), wy = r * sqrt(i10 * i10 + i11 * i11);",
+     "const double wx = 0.5 * r * sqrt(i00 * i00 + i01 * i01), wy = 0.5 * r * sqrt(i10 * i10 + i11 * i11);"),
+    ("default h", "2.0 * P->radii[m] * P->radii[m] / 9.0", "2.0 * P->radii[m] * P->radii[m] / 4.5"),
+    ("green ratio not applied to radius", "const double r = P->radii[m] * kappa;", "const double r = P->radii[m];"),
+    ("CFA GRBG wrong", "{1, 0, 2, 1}, /* GRBG */", "{1, 2, 0, 1}, /* GRBG */"),
+    ("variance sandwich uses A", "var += g[i] * B[i][j] * g[j];", "var += g[i] * A[i][j] * g[j];"),
+    ("fallback skipped", "for (int o = M; o >= 0; --o) {", "for (int o = M; o >= M; --o) {"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,orig,bad", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(name, orig, bad):
+    with open(SRC) as fh:
+        text = fh.read()
+    assert text.count(orig) >= 1, f"mutation anchor not found: {orig}"
+    mutated = text.replace(orig, bad, 1)
+    with tempfile.TemporaryDirectory() as tmp:
+        src = os.path.join(tmp, "lpa_oracle.c")
+        with open(src, "w") as fh:
+            fh.write(mutated)
+        shutil.copy(os.path.join(ROOT, "oracle", "lpa_oracle.h"), tmp)
+        lib = os.path.join(tmp, "libmut.so")
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-o", lib,
+                        src, "-lm"], check=True)
+        env = dict(os.environ, LPA_ORACLE_LIB_OVERRIDE=lib)
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"planted mistake '{name}' passed every pin:\n{r.stdout[-2000:]}"

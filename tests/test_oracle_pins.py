@@ -163,6 +163,14 @@ def test_bruteforce_lstsq(order):
                 C, *_ = np.linalg.lstsq(Phi * sw[:, None], fh * sw, rcond=None)
                 a = np.linalg.pinv(Phi * sw[:, None])[0] * sw
                 v_ref = np.sum(a * a * var)
+                # smallest pivot of the Jacobi-equilibrated normal matrix (numpy Cholesky)
+                A = (Phi * (k / var)[:, None]).T @ Phi
+                dsc = 1.0 / np.sqrt(np.diag(A))
+                try:
+                    rho_ref = np.min(np.diag(np.linalg.cholesky(A * np.outer(dsc, dsc))) ** 2)
+                except np.linalg.LinAlgError:
+                    rho_ref = 0.0
+                assert fit["rho"] == pytest.approx(rho_ref, rel=1e-6, abs=1e-9)
                 if not fit["valid"]:
                     continue
                 assert fit["yhat"] == pytest.approx(C[0], rel=1e-9, abs=1e-9)
