@@ -1,0 +1,205 @@
+/*
+ * lpa.h -- C ABI of the MI355X (gfx950) library for multi-sensor HDR video
+ * reconstruction by local polynomial approximation (LPA) with ICI window
+ * selection, after Kronander, Gustavson, Bonnet, Ynnerman and Unger, "A
+ * Unified Framework for Multi-Sensor HDR Video Reconstruction" (arXiv
+ * 1308.4908).
+ *
+ * What one reconstruction computes, per output pixel j and colour channel c:
+ *   - every raw CFA sample y of every sensor s is turned into a radiance
+ *     estimate f = (y - b_s) / (g_s n_s) (Sec. 6, eq. Efsi) and a variance
+ *     estimate (g_s^2 n_s f + Var r_s) / (g_s n_s)^2 (Sec. 6.1,
+ *     eq. varianceestiamte; shot term clamped at 0); samples with
+ *     y >= saturation are dropped (end of Sec. 6.1);
+ *   - the sample sits at X = T_s(x) on the reference plane (Sec. 4.2), the
+ *     output pixel at X_j = O(u, v) (arbitrary output grid, Sec. 3);
+ *   - for each window radius r_m (ascending) the order-M local polynomial
+ *     (Sec. 5.1) is fitted by weighted least squares, eq. (wlsqe), with weight
+ *     K(|X - X_j|) / sigma^2, K(d) = exp(-d^2/h) - exp(-r^2/h) on d < r
+ *     (isotropic Gaussian window of Sec. 5.3.1, truncated to vanish at r);
+ *     a fit is valid when its support has at least as many samples as basis
+ *     terms and the smallest pivot of the equilibrated normal matrix is at
+ *     least tau_inv (the "invertible" rule of Sec. 5.3.1 made numeric);
+ *   - intersection of confidence intervals (ICI) picks the radius: intervals
+ *     C0 +- gamma * sd(C0) of the valid radii are intersected in ascending
+ *     order and the last radius with a non-empty intersection is kept (the
+ *     LPA-ICI rule of Goldenshluger-Nemirovski / Katkovnik; not in the paper);
+ *   - if no radius is valid at order M the same supports are refitted at
+ *     order M-1, ..., 0; if none is valid the output is NaN.
+ *   The output is C0 per channel, in photo-electrons per unit exposure.
+ *
+ * Conventions: sensor pixel centres are at integer (x = column, y = row);
+ * affine maps are [a0 a1 a2; a3 a4 a5]: X = a0 x + a1 y + a2,
+ * Y = a3 x + a4 y + a5.  Radii and h are in reference-plane units.
+ *
+ * Errors: every call returns an lpa_status.  Arguments are validated before
+ * anything is enqueued; on an error nothing is enqueued and outputs are left
+ * untouched.  lpa_last_error() gives a thread-local message.  No C++
+ * exception crosses this interface.  After a device error the context is
+ * sticky-failed: every call on it returns LPA_ERR_DEVICE until it is
+ * destroyed.
+ */
+#ifndef LPA_H
+#define LPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LPA_MAX_SENSORS 8
+#define LPA_MAX_SCALES 8
+
+typedef int32_t lpa_status;
+enum {
+  LPA_OK = 0,
+  LPA_NOT_READY = 1,        /* lpa_poll: the frame is not finished yet          */
+  LPA_AGAIN = 2,            /* lpa_submit: the admission queue is full          */
+  LPA_ERR_INVALID_ARG = -1, /* argument failed validation; nothing enqueued    */
+  LPA_ERR_OOM = -2,         /* device memory or HBM budget exhausted            */
+  LPA_ERR_DEVICE = -3,      /* HIP runtime / device error (context now failed) */
+  LPA_ERR_UNSUPPORTED = -4, /* valid request this build cannot run              */
+  LPA_ERR_INTERNAL = -5
+};
+
+enum { LPA_CFA_RGGB = 0, LPA_CFA_BGGR = 1, LPA_CFA_GRBG = 2, LPA_CFA_GBRG = 3 };
+enum { LPA_DTYPE_U16 = 0, LPA_DTYPE_F32 = 1 }; /* raw sample type (F32: DN as float, tests) */
+enum { LPA_MEM_DEVICE = 0, LPA_MEM_HOST = 1 }; /* where lpa_frame.raw points               */
+
+/* Sample storage between raw decode and the fit:
+ *   FUSED   raw samples are decoded straight into LDS by the fit kernel;
+ *   FP32    a pre-pass writes FP32 radiance + FP32 inverse variance planes;
+ *   FP16    a pre-pass writes FP16 normalised radiance (y - b) * 2^-bit_depth,
+ *           round-to-nearest-even, +Inf for masked samples; the fit kernel
+ *           decodes radiance and variance from it. */
+enum { LPA_STORE_FUSED = 0, LPA_STORE_FP32 = 1, LPA_STORE_FP16 = 2 };
+
+/* lpa_params.flags */
+#define LPA_FLAG_NO_FP64_FALLBACK 0x1u /* never redo ill-conditioned order-2 solves in FP64 */
+
+/* One sensor of a rig (Sec. 3, Sec. 4, Sec. 6). */
+typedef struct {
+  int32_t width, height; /* pixels                                          */
+  int32_t cfa;           /* LPA_CFA_*                                       */
+  int32_t bit_depth;     /* ADC bits (FP16 storage normalises by 2^bits)    */
+  double affine[6];      /* T_s: sensor pixel centre -> reference plane     */
+  double exposure;       /* n_s * t_s (relative exposure, > 0)              */
+  double gain;           /* g_s [DN / e-] (> 0)                             */
+  double read_sigma;     /* sqrt(Var[r_s]) [DN] (> 0)                       */
+  double black_level;    /* b_s [DN]                                        */
+  double saturation;     /* a sample is masked iff y >= saturation [DN]     */
+} lpa_sensor_desc;
+
+typedef struct {
+  int32_t n_sensors; /* 1..LPA_MAX_SENSORS */
+  const lpa_sensor_desc* sensors;
+} lpa_rig_desc;
+
+/* Reconstruction parameters (Sec. 5.3: order M, window, scale). */
+typedef struct {
+  int32_t out_w, out_h;   /* output grid                                            */
+  double out_affine[6];   /* O: output pixel (u = col, v = row) -> reference plane  */
+  int32_t order;          /* M in {0, 1, 2}                                         */
+  int32_t n_scales;       /* 1..LPA_MAX_SCALES window radii                         */
+  double radii[LPA_MAX_SCALES]; /* ascending, > 0                                   */
+  double h[LPA_MAX_SCALES];     /* window parameter; <= 0 selects 2 r^2 / 9         */
+  double gamma;           /* ICI interval half-width in standard deviations (> 0)  */
+  double green_ratio;     /* green radius / h scale kappa_G (> 0; 1 = same as R/B)  */
+  int32_t storage;        /* LPA_STORE_*                                            */
+  double tau_inv;         /* validity threshold; <= 0 selects 1e-5                  */
+  double tau_fp64;        /* order-2 FP64 re-solve below this pivot; <= 0: 1e-3     */
+  uint32_t flags;         /* LPA_FLAG_*                                             */
+} lpa_params;
+
+/* One frame: a raw plane per sensor (row-major, row_pitch_bytes apart). */
+typedef struct {
+  int32_t n_sensors;
+  const void* raw[LPA_MAX_SENSORS];
+  int64_t row_pitch_bytes[LPA_MAX_SENSORS];
+  int32_t dtype;  /* LPA_DTYPE_*                                   */
+  int32_t memory; /* LPA_MEM_*: lpa_reconstruct needs DEVICE;       */
+                  /* lpa_submit accepts HOST (copied at admission)  */
+} lpa_frame;
+
+/* Output: RGB float32, pixel-interleaved rows; optional per-channel code map
+ * (order_used << 4 | radius index, 0xFF where nothing is valid) and optional
+ * per-channel standard deviation of the output value (the square root of the
+ * estimator's variance, NaN where nothing is valid).  Device pointers. */
+typedef struct {
+  float* rgb;
+  int64_t row_pitch_bytes;
+  uint8_t* scale_map;         /* may be NULL                     */
+  int64_t scale_map_pitch;    /* bytes between scale_map rows    */
+  float* sd_map;              /* may be NULL                     */
+  int64_t sd_map_pitch;       /* bytes between sd_map rows       */
+} lpa_output;
+
+/* Status and timestamps of a submitted frame (CLOCK_MONOTONIC ns). */
+typedef struct {
+  int32_t status;         /* LPA_OK, LPA_NOT_READY or an error */
+  int32_t batch_size;     /* frames in the launch that ran it  */
+  int64_t t_arrival_ns, t_admit_ns, t_start_ns, t_done_ns;
+} lpa_result;
+
+typedef struct lpa_ctx lpa_ctx;
+typedef struct lpa_rig lpa_rig;
+
+/* Create a context on HIP device `device` with an HBM budget (bytes) for the
+ * library's own buffers (0 = 90% of free memory).  The context owns its
+ * streams, scratch planes, autotune cache and serving scheduler. */
+lpa_status lpa_create_ctx(int device, size_t hbm_budget_bytes, lpa_ctx** out);
+/* Wait for all work of the context, stop its scheduler, free everything. */
+lpa_status lpa_destroy_ctx(lpa_ctx* ctx);
+
+/* Create a rig: the descriptor is validated and copied (caller may free it);
+ * the per-sensor calibration and noise constants stay resident on the
+ * device until lpa_destroy_rig.  Validation: 1..8 sensors, sizes >= 1,
+ * gain, exposure, read_sigma > 0, invertible affine, finite values,
+ * saturation > black_level, 1 <= bit_depth <= 16. */
+lpa_status lpa_create_rig(lpa_ctx* ctx, const lpa_rig_desc* desc, lpa_rig** out);
+lpa_status lpa_destroy_rig(lpa_rig* rig);
+
+/* Reconstruct one frame, stream-ordered on `hip_stream` (a hipStream_t; NULL
+ * = the null stream).  raw and out are device pointers borrowed until the
+ * stream passes this work.  Returns after enqueueing. */
+lpa_status lpa_reconstruct(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
+                           const lpa_output* out, void* hip_stream);
+
+/* The plain per-frame form: FP32 radiance / inverse-variance planes from a
+ * separate pre-pass launch, then one fit launch with a fixed 16x16 tile (no
+ * tuning).  Same results contract as lpa_reconstruct. */
+lpa_status lpa_reconstruct_plain(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
+                                 const lpa_output* out, void* hip_stream);
+
+/* Reconstruct n frames (each with its own rig and parameters) in one
+ * persistent launch that pulls output tiles from a device work queue.  The
+ * launch is recorded into a HIP graph and replayed while the frame shapes
+ * are unchanged (`reuse` != 0 lets the library keep that graph).  Each
+ * frame's result is bit-identical to lpa_reconstruct of that frame alone. */
+lpa_status lpa_reconstruct_batch(lpa_ctx* ctx, int32_t n, lpa_rig* const* rigs,
+                                 const lpa_frame* frames, const lpa_params* params,
+                                 const lpa_output* outs, void* hip_stream);
+
+/* Serving: queue a frame that arrived at `arrival_ns` (CLOCK_MONOTONIC).  Host
+ * raw planes are copied into a device slot when the HBM budget admits the
+ * frame; frames admitted while others run are batched into the next launch,
+ * which overlaps the running one on a second stream.  raw and out are
+ * borrowed until lpa_poll reports a terminal status.  Returns LPA_AGAIN if
+ * the admission queue (1024 frames) is full. */
+lpa_status lpa_submit(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
+                      const lpa_output* out, int64_t arrival_ns, uint64_t* ticket);
+/* Non-blocking: LPA_NOT_READY until the frame is done; then its result.  A
+ * ticket can be polled until the context is destroyed. */
+lpa_status lpa_poll(lpa_ctx* ctx, uint64_t ticket, lpa_result* out);
+/* Block until every submitted frame is finished. */
+lpa_status lpa_drain(lpa_ctx* ctx);
+
+/* Thread-local message of the last non-OK status returned on this thread. */
+const char* lpa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -67,13 +67,17 @@ class _Fit(ctypes.Structure):
         ("rho", ctypes.c_double),
         ("c1x", ctypes.c_double),
         ("c1y", ctypes.c_double),
+        ("l1f", ctypes.c_double),
+        ("sens_y", ctypes.c_double),
+        ("sens_v", ctypes.c_double),
         ("n", ctypes.c_int32),
         ("valid", ctypes.c_int32),
     ]
 
 
 FIT_DTYPE = np.dtype(
-    [("yhat", "f8"), ("var", "f8"), ("rho", "f8"), ("c1x", "f8"), ("c1y", "f8"),
+    [("yhat", "f8"), ("var", "f8"), ("rho", "f8"), ("c1x", "f8"), ("c1y", "f8"), ("l1f", "f8"),
+     ("sens_y", "f8"), ("sens_v", "f8"),
      ("n", "i4"), ("valid", "i4")],
     align=True,
 )
@@ -106,7 +110,7 @@ def _load():
         lib.orc_reconstruct.argtypes = [
             ctypes.POINTER(_Sensor), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
             ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
-            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ]
         lib.orc_sample_radiance.restype = ctypes.c_int
         lib.orc_sample_radiance.argtypes = [
@@ -118,7 +122,7 @@ def _load():
         lib.orc_ici_select.restype = ctypes.c_int
         lib.orc_ici_select.argtypes = [
             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
-            ctypes.POINTER(ctypes.c_double),
+            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
         ]
         _lib = lib
     return _lib
@@ -167,7 +171,7 @@ def reconstruct(sensors, raws, params, pixels=None, want_fits=False, exhaustive=
     numeric dtype; converted exactly to float64); params : parameter dict;
     pixels : optional (n, 2) int array of (u, v) output pixels (default: the
     whole grid, row-major).  Returns a dict with ``rgb`` (n, 3) float64,
-    ``scale_map`` (n, 3) uint8, ``margin`` (n, 3) and, if asked, ``fits``
+    ``scale_map`` (n, 3) uint8, ``margin`` (n, 3), ``gap`` (n, 3) and, if asked, ``fits``
     (n, 3, n_scales, 3) structured array (see FIT_DTYPE).
     """
     lib = _load()
@@ -190,14 +194,15 @@ def reconstruct(sensors, raws, params, pixels=None, want_fits=False, exhaustive=
     rgb = np.empty((n, 3), np.float64)
     smap = np.empty((n, 3), np.uint8)
     margin = np.empty((n, 3), np.float64)
+    gap = np.empty((n, 3), np.float64)
     fits = np.zeros((n, 3, prm.n_scales, 3), FIT_DTYPE) if want_fits else None
     rc = lib.orc_reconstruct(
         sens, ns, ptrs, ctypes.byref(prm), pix_ptr, n, rgb.ctypes.data, smap.ctypes.data,
-        margin.ctypes.data, fits.ctypes.data if fits is not None else None,
+        margin.ctypes.data, gap.ctypes.data, fits.ctypes.data if fits is not None else None,
     )
     if rc != 0:
         raise ValueError(f"oracle rejected its arguments (code {rc})")
-    out = {"rgb": rgb, "scale_map": smap, "margin": margin}
+    out = {"rgb": rgb, "scale_map": smap, "margin": margin, "gap": gap}
     if fits is not None:
         out["fits"] = fits
     return out
@@ -219,12 +224,13 @@ def cfa_channel(cfa, x: int, y: int) -> int:
 
 
 def ici_select(yhat, var, valid, gamma: float = 2.0):
-    """The ICI rule on given per-scale estimates: (chosen index or -1, margin)."""
+    """The ICI rule on given per-scale estimates: (chosen index or -1, margin, gap)."""
     lib = _load()
     y = np.ascontiguousarray(yhat, np.float64)
     v = np.ascontiguousarray(var, np.float64)
     ok = np.ascontiguousarray(valid, np.int32)
     mu = ctypes.c_double()
+    gp = ctypes.c_double()
     k = lib.orc_ici_select(len(y), y.ctypes.data, v.ctypes.data, ok.ctypes.data, float(gamma),
-                           ctypes.byref(mu))
-    return k, mu.value
+                           ctypes.byref(mu), ctypes.byref(gp))
+    return k, mu.value, gp.value

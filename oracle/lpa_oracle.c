@@ -55,8 +55,8 @@ int orc_sample_radiance(const orc_sensor* s, double y, double* f_hat, double* va
  * the valid scales are intersected in ascending order of radius; the last
  * scale whose running intersection is non-empty (L <= U) is chosen. */
 int orc_ici_select(int32_t n_scales, const double* yhat, const double* var, const int32_t* valid,
-                   double gamma, double* margin_out) {
-  double lo_run = -INFINITY, hi_run = INFINITY, margin = INFINITY;
+                   double gamma, double* margin_out, double* gap_out) {
+  double lo_run = -INFINITY, hi_run = INFINITY, margin = INFINITY, gap = INFINITY;
   int chosen = -1;
   for (int m = 0; m < n_scales; ++m) {
     if (!valid[m]) continue;
@@ -67,6 +67,7 @@ int orc_ici_select(int32_t n_scales, const double* yhat, const double* var, cons
     if (chosen >= 0) {
       const double mu = fabs(hi_run - lo_run) / (gamma * sd);
       if (mu < margin) margin = mu;
+      if (fabs(hi_run - lo_run) < gap) gap = fabs(hi_run - lo_run);
     }
     if (lo_run <= hi_run)
       chosen = m;
@@ -74,6 +75,7 @@ int orc_ici_select(int32_t n_scales, const double* yhat, const double* var, cons
       break;
   }
   if (margin_out) *margin_out = margin;
+  if (gap_out) *gap_out = gap;
   return chosen;
 }
 
@@ -205,6 +207,8 @@ static void chol_solve(int n, const double L[NB_MAX][NB_MAX], const double* rhs,
  * is sum K_k^2 / sigma_k^2 phi phi^T since Sigma = diag(sigma_k^2) (R8). */
 static void fit_order(const sample_list* S, int n, double tau_inv, orc_fit* out) {
   double A[NB_MAX][NB_MAX] = {{0}}, B[NB_MAX][NB_MAX] = {{0}}, b[NB_MAX] = {0};
+  /* sums of absolute terms (diagnostics: rounding sensitivity, not the fit) */
+  double Aa[NB_MAX][NB_MAX] = {{0}}, Ba[NB_MAX][NB_MAX] = {{0}}, ba[NB_MAX] = {0};
   for (int64_t k = 0; k < S->n; ++k) {
     const orc_sample* s = &S->v[k];
     double phi[NB_MAX];
@@ -213,9 +217,12 @@ static void fit_order(const sample_list* S, int n, double tau_inv, orc_fit* out)
     const double w2 = s->k * s->k * s->ivar;
     for (int i = 0; i < n; ++i) {
       b[i] += w * s->f * phi[i];
+      ba[i] += fabs(w * s->f * phi[i]);
       for (int j = 0; j < n; ++j) {
         A[i][j] += w * phi[i] * phi[j];
         B[i][j] += w2 * phi[i] * phi[j];
+        Aa[i][j] += fabs(w * phi[i] * phi[j]);
+        Ba[i][j] += fabs(w2 * phi[i] * phi[j]);
       }
     }
   }
@@ -224,6 +231,9 @@ static void fit_order(const sample_list* S, int n, double tau_inv, orc_fit* out)
   out->var = NAN;
   out->c1x = 0.0;
   out->c1y = 0.0;
+  out->l1f = 0.0;
+  out->sens_y = 0.0;
+  out->sens_v = 0.0;
   out->rho = 0.0;
   out->valid = 0;
 
@@ -252,6 +262,42 @@ static void fit_order(const sample_list* S, int n, double tau_inv, orc_fit* out)
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) var += g[i] * B[i][j] * g[j];
 
+  /* equivalent-kernel weights a_k = (g . phi_k) w_k, C0 = sum_k a_k f_k */
+  double l1f = 0.0;
+  for (int64_t k = 0; k < S->n; ++k) {
+    const orc_sample* s = &S->v[k];
+    double phi[NB_MAX];
+    basis(s->dx, s->dy, phi);
+    double gp = 0.0;
+    for (int i = 0; i < n; ++i) gp += g[i] * phi[i];
+    l1f += fabs(gp * s->k * s->ivar * s->f);
+  }
+  out->l1f = l1f;
+  /* rounding sensitivities (see lpa_oracle.h) */
+  double Ainv[NB_MAX][NB_MAX];
+  for (int j = 0; j < n; ++j) {
+    double e[NB_MAX], col[NB_MAX];
+    for (int i = 0; i < n; ++i) e[i] = (i == j) ? scale[i] : 0.0;
+    chol_solve(n, L, e, col);
+    for (int i = 0; i < n; ++i) Ainv[i][j] = scale[i] * col[i];
+  }
+  double sy = 0.0, sv = 0.0, Bg[NB_MAX], Aag[NB_MAX];
+  for (int i = 0; i < n; ++i) {
+    double t = 0.0, q = 0.0;
+    for (int j = 0; j < n; ++j) {
+      sy += fabs(g[i]) * Aa[i][j] * fabs(C[j]);
+      sv += fabs(g[i]) * Ba[i][j] * fabs(g[j]);
+      t += B[i][j] * g[j];
+      q += Aa[i][j] * fabs(g[j]);
+    }
+    sy += fabs(g[i]) * ba[i];
+    Bg[i] = t;
+    Aag[i] = q;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) sv += 2.0 * fabs(Bg[i]) * fabs(Ainv[i][j]) * Aag[j];
+  out->sens_y = sy;
+  out->sens_v = sv;
   out->yhat = C[0];
   out->var = var;
   if (n >= 3) {
@@ -263,7 +309,7 @@ static void fit_order(const sample_list* S, int n, double tau_inv, orc_fit* out)
 
 int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
                     const orc_params* P, const int32_t* pixels, int64_t n_pixels, double* rgb,
-                    uint8_t* scale_map, double* margin, orc_fit* fits) {
+                    uint8_t* scale_map, double* margin, double* gap, orc_fit* fits) {
   if (!sensors || !raw || !P || !rgb) return -1;
   if (n_sensors < 1 || n_sensors > ORC_MAX_SENSORS) return -2;
   if (P->order < 0 || P->order > 2) return -3;
@@ -303,7 +349,7 @@ int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* 
       }
 
       /* Selection: ICI at the highest order with any valid scale (R8, R9). */
-      double value = NAN, mu = INFINITY;
+      double value = NAN, mu = INFINITY, gp = INFINITY;
       int code = 0xFF;
       for (int o = M; o >= 0; --o) {
         double yh[ORC_MAX_SCALES], vr[ORC_MAX_SCALES];
@@ -316,7 +362,7 @@ int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* 
           any |= ok[m];
         }
         if (!any) continue;
-        const int chosen = orc_ici_select(nS, yh, vr, ok, P->gamma, &mu);
+        const int chosen = orc_ici_select(nS, yh, vr, ok, P->gamma, &mu, &gp);
         value = yh[chosen];
         code = (o << 4) | chosen;
         break;
@@ -324,6 +370,7 @@ int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* 
       rgb[3 * p + c] = value;
       if (scale_map) scale_map[3 * p + c] = (uint8_t)code;
       if (margin) margin[3 * p + c] = mu;
+      if (gap) gap[3 * p + c] = gp;
       if (fits)
         for (int m = 0; m < nS; ++m)
           for (int o = 0; o < 3; ++o) fits[((p * 3 + c) * nS + m) * 3 + o] = local[m][o];

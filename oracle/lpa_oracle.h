@@ -88,6 +88,12 @@ typedef struct {
   double var;    /* variance of C0 (sandwich formula)             */
   double rho;    /* smallest equilibrated Cholesky pivot (0 if not SPD) */
   double c1x, c1y; /* gradient C1 (orders >= 1), else 0           */
+  double l1f;    /* sum_k |a_k f_k| with C0 = sum_k a_k f_k: the size of the terms
+                    the estimate sums (its rounding-error scale) */
+  double sens_y; /* first-order bound on |dC0| per unit relative perturbation of
+                    every moment term: |g|'|b|abs + |g|'|A|abs|C|, with g = A^-1 e0,
+                    |A|abs = sum w |phi phi'|, |b|abs = sum w |f phi| */
+  double sens_v; /* same for var(C0): 2 |B g|' |A^-1| |A|abs |g| + |g|' |B|abs |g| */
   int32_t n;     /* number of samples with positive window weight */
   int32_t valid; /* n >= basis size and rho >= tau_inv            */
 } orc_fit;
@@ -103,13 +109,15 @@ typedef struct {
  *   margin      : optional, n_pixels * 3: smallest ICI decision margin
  *                 |U - L| / (Gamma * sqrt(var)) over the steps taken (+Inf if
  *                 fewer than two valid scales)
+ *   gap         : optional, n_pixels * 3: smallest |U - L| over those steps
+ *                 (radiance units; +Inf if fewer than two valid scales)
  *   fits        : optional, n_pixels * 3 * n_scales * 3 entries, index
  *                 ((p * 3 + c) * n_scales + m) * 3 + order
  * Returns 0 on success, a negative value on invalid arguments.
  */
 int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
                     const orc_params* params, const int32_t* pixels, int64_t n_pixels, double* rgb,
-                    uint8_t* scale_map, double* margin, orc_fit* fits);
+                    uint8_t* scale_map, double* margin, double* gap, orc_fit* fits);
 
 /* Radiance estimate and variance estimate of one sample (Sec. 6, 6.1).
  * Returns 1 if the sample is usable (not saturated), 0 if masked. */
@@ -120,9 +128,10 @@ int orc_cfa_channel(int32_t cfa, int32_t x, int32_t y);
 
 /* The ICI rule on given per-scale estimates (used by the unit tests on worked
  * examples).  valid[m] != 0 marks a usable scale.  Returns the chosen scale or
- * -1 if none is valid; *margin_out receives the smallest decision margin. */
+ * -1 if none is valid; *margin_out receives the smallest decision margin and
+ * *gap_out the smallest |U - L| (either may be NULL). */
 int orc_ici_select(int32_t n_scales, const double* yhat, const double* var, const int32_t* valid,
-                   double gamma, double* margin_out);
+                   double gamma, double* margin_out, double* gap_out);
 
 #ifdef __cplusplus
 }

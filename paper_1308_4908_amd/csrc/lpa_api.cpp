@@ -1,0 +1,475 @@
+// lpa_api.cpp -- the C ABI of include/lpa.h: contexts, rigs, argument
+// validation, launch-descriptor construction and the single-frame paths.
+// Batched and served paths live in lpa_batch.cpp / lpa_serve.cpp.
+#include "lpa_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+namespace lpa {
+
+thread_local char g_last_error[512] = "";
+
+lpa_status set_error(lpa_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+lpa_status device_error(lpa_ctx* ctx, hipError_t e, const char* what) {
+  if (ctx) ctx->failed.store(true);
+  return set_error(LPA_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Colour (0 R, 1 G, 2 B) of CFA cell [2 * row parity + column parity].
+static const int kCfaTable[4][4] = {
+    {0, 1, 1, 2},  // RGGB
+    {2, 1, 1, 0},  // BGGR
+    {1, 0, 2, 1},  // GRBG
+    {1, 2, 0, 1},  // GBRG
+};
+
+static bool finite6(const double* a) {
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+lpa_status validate_rig(const lpa_rig_desc* d) {
+  if (!d || !d->sensors) return set_error(LPA_ERR_INVALID_ARG, "rig descriptor is NULL");
+  if (d->n_sensors < 1 || d->n_sensors > LPA_MAX_SENSORS)
+    return set_error(LPA_ERR_INVALID_ARG, "n_sensors %d outside 1..%d", d->n_sensors, LPA_MAX_SENSORS);
+  for (int s = 0; s < d->n_sensors; ++s) {
+    const lpa_sensor_desc& S = d->sensors[s];
+    if (S.width < 1 || S.height < 1 || S.width > (1 << 16) || S.height > (1 << 16))
+      return set_error(LPA_ERR_INVALID_ARG, "sensor %d: size %dx%d invalid", s, S.width, S.height);
+    if (S.cfa < 0 || S.cfa > 3) return set_error(LPA_ERR_INVALID_ARG, "sensor %d: cfa %d invalid", s, S.cfa);
+    if (S.bit_depth < 1 || S.bit_depth > 16)
+      return set_error(LPA_ERR_INVALID_ARG, "sensor %d: bit_depth %d invalid", s, S.bit_depth);
+    if (!finite6(S.affine)) return set_error(LPA_ERR_INVALID_ARG, "sensor %d: affine not finite", s);
+    const double det = S.affine[0] * S.affine[4] - S.affine[1] * S.affine[3];
+    if (!(std::fabs(det) > 1e-12)) return set_error(LPA_ERR_INVALID_ARG, "sensor %d: affine not invertible", s);
+    if (!(S.exposure > 0) || !std::isfinite(S.exposure))
+      return set_error(LPA_ERR_INVALID_ARG, "sensor %d: exposure must be > 0", s);
+    if (!(S.gain > 0) || !std::isfinite(S.gain)) return set_error(LPA_ERR_INVALID_ARG, "sensor %d: gain must be > 0", s);
+    if (!(S.read_sigma > 0) || !std::isfinite(S.read_sigma))
+      return set_error(LPA_ERR_INVALID_ARG, "sensor %d: read_sigma must be > 0", s);
+    if (!std::isfinite(S.black_level) || !(S.saturation > S.black_level))
+      return set_error(LPA_ERR_INVALID_ARG, "sensor %d: saturation must exceed black_level", s);
+  }
+  return LPA_OK;
+}
+
+lpa_status resolve_params(const lpa_params* p, Resolved* r) {
+  if (!p) return set_error(LPA_ERR_INVALID_ARG, "params is NULL");
+  if (p->out_w < 1 || p->out_h < 1 || p->out_w > (1 << 16) || p->out_h > (1 << 16))
+    return set_error(LPA_ERR_INVALID_ARG, "output size %dx%d invalid", p->out_w, p->out_h);
+  if (!finite6(p->out_affine)) return set_error(LPA_ERR_INVALID_ARG, "out_affine not finite");
+  if (p->order < 0 || p->order > 2) return set_error(LPA_ERR_INVALID_ARG, "order %d outside 0..2", p->order);
+  if (p->n_scales < 1 || p->n_scales > LPA_MAX_SCALES)
+    return set_error(LPA_ERR_INVALID_ARG, "n_scales %d outside 1..%d", p->n_scales, LPA_MAX_SCALES);
+  for (int m = 0; m < p->n_scales; ++m) {
+    if (!(p->radii[m] > 0) || !std::isfinite(p->radii[m]))
+      return set_error(LPA_ERR_INVALID_ARG, "radius %d must be > 0", m);
+    if (m > 0 && !(p->radii[m] > p->radii[m - 1]))
+      return set_error(LPA_ERR_INVALID_ARG, "radii must be strictly ascending");
+    if (!std::isfinite(p->h[m])) return set_error(LPA_ERR_INVALID_ARG, "h[%d] not finite", m);
+  }
+  if (p->n_scales > 1 && (!(p->gamma > 0) || !std::isfinite(p->gamma)))
+    return set_error(LPA_ERR_INVALID_ARG, "gamma must be > 0");
+  if (!(p->green_ratio > 0) || !std::isfinite(p->green_ratio))
+    return set_error(LPA_ERR_INVALID_ARG, "green_ratio must be > 0");
+  if (p->storage < LPA_STORE_FUSED || p->storage > LPA_STORE_FP16)
+    return set_error(LPA_ERR_INVALID_ARG, "storage %d invalid", p->storage);
+  if (!std::isfinite(p->tau_inv) || !std::isfinite(p->tau_fp64))
+    return set_error(LPA_ERR_INVALID_ARG, "thresholds not finite");
+  r->p = *p;
+  r->tau_inv = p->tau_inv > 0 ? p->tau_inv : 1e-5;
+  r->tau_fp64 = p->tau_fp64 > 0 ? p->tau_fp64 : 1e-3;
+  r->gamma = p->n_scales > 1 ? p->gamma : 1.0;
+  for (int m = 0; m < p->n_scales; ++m) r->h[m] = p->h[m] > 0 ? p->h[m] : 2.0 * p->radii[m] * p->radii[m] / 9.0;
+  return LPA_OK;
+}
+
+lpa_status validate_frame(const lpa_rig* rig, const lpa_frame* f, bool need_device) {
+  if (!f) return set_error(LPA_ERR_INVALID_ARG, "frame is NULL");
+  if (f->n_sensors != rig->n) return set_error(LPA_ERR_INVALID_ARG, "frame has %d sensors, rig has %d", f->n_sensors, rig->n);
+  if (f->dtype != LPA_DTYPE_U16 && f->dtype != LPA_DTYPE_F32) return set_error(LPA_ERR_INVALID_ARG, "dtype %d invalid", f->dtype);
+  if (f->memory != LPA_MEM_DEVICE && f->memory != LPA_MEM_HOST) return set_error(LPA_ERR_INVALID_ARG, "memory %d invalid", f->memory);
+  if (need_device && f->memory != LPA_MEM_DEVICE)
+    return set_error(LPA_ERR_INVALID_ARG, "lpa_reconstruct needs device-resident frames");
+  const int64_t es = f->dtype == LPA_DTYPE_U16 ? 2 : 4;
+  for (int s = 0; s < rig->n; ++s) {
+    if (!f->raw[s]) return set_error(LPA_ERR_INVALID_ARG, "raw[%d] is NULL", s);
+    if (f->row_pitch_bytes[s] < es * rig->desc[s].width || f->row_pitch_bytes[s] % es)
+      return set_error(LPA_ERR_INVALID_ARG, "row_pitch_bytes[%d] = %lld invalid", s, (long long)f->row_pitch_bytes[s]);
+  }
+  return LPA_OK;
+}
+
+lpa_status validate_output(const lpa_params* p, const lpa_output* o) {
+  if (!o || !o->rgb) return set_error(LPA_ERR_INVALID_ARG, "output rgb is NULL");
+  if (o->row_pitch_bytes < (int64_t)12 * p->out_w || o->row_pitch_bytes % 4)
+    return set_error(LPA_ERR_INVALID_ARG, "output row pitch %lld invalid", (long long)o->row_pitch_bytes);
+  if (o->scale_map && o->scale_map_pitch < (int64_t)3 * p->out_w)
+    return set_error(LPA_ERR_INVALID_ARG, "scale_map pitch %lld invalid", (long long)o->scale_map_pitch);
+  if (o->sd_map && (o->sd_map_pitch < (int64_t)12 * p->out_w || o->sd_map_pitch % 4))
+    return set_error(LPA_ERR_INVALID_ARG, "sd_map pitch %lld invalid", (long long)o->sd_map_pitch);
+  return LPA_OK;
+}
+
+// Per-sensor constants that do not depend on the launch.
+void rig_constants(const lpa_sensor_desc& S, SensorK* k) {
+  std::memset(k, 0, sizeof(*k));
+  const double* a = S.affine;
+  for (int i = 0; i < 6; ++i) k->fwd[i] = a[i];
+  const double det = a[0] * a[4] - a[1] * a[3];
+  k->inv[0] = a[4] / det;
+  k->inv[1] = -a[1] / det;
+  k->inv[2] = (a[1] * a[5] - a[4] * a[2]) / det;
+  k->inv[3] = -a[3] / det;
+  k->inv[4] = a[0] / det;
+  k->inv[5] = (a[3] * a[2] - a[0] * a[5]) / det;
+  k->rownorm[0] = std::sqrt(k->inv[0] * k->inv[0] + k->inv[1] * k->inv[1]);
+  k->rownorm[1] = std::sqrt(k->inv[3] * k->inv[3] + k->inv[4] * k->inv[4]);
+  const double ge = S.gain * S.exposure;
+  k->inv_ge = (float)(1.0 / ge);
+  k->gain = (float)S.gain;
+  k->read_var = (float)(S.read_sigma * S.read_sigma);
+  k->black = (float)S.black_level;
+  k->sat = (float)S.saturation;
+  k->norm_decode = std::ldexp(1.0f, S.bit_depth);
+  k->width = S.width;
+  k->height = S.height;
+  for (int c = 0; c < 3; ++c) {
+    int n = 0;
+    for (int oy = 0; oy < 2; ++oy)
+      for (int ox = 0; ox < 2; ++ox)
+        if (kCfaTable[S.cfa][2 * oy + ox] == c && n < 2) {
+          k->sub_ox[c][n] = (int8_t)ox;
+          k->sub_oy[c][n] = (int8_t)oy;
+          ++n;
+        }
+    k->sub_n[c] = (int8_t)n;
+  }
+}
+
+// Fill the launch-dependent parts of a descriptor.  Returns false if the
+// LDS footprint of the requested tile does not fit.
+lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output* out, int src_kind,
+                        const void* const* srcs, const int64_t* pitches, int tile_w, int tile_h,
+                        LaunchK* K) {
+  const lpa_params& p = R.p;
+  std::memset(K, 0, sizeof(*K));
+  for (int i = 0; i < 6; ++i) K->out_affine[i] = p.out_affine[i];
+  K->out_w = p.out_w;
+  K->out_h = p.out_h;
+  K->tile_w = tile_w;
+  K->tile_h = tile_h;
+  K->tiles_x = (p.out_w + tile_w - 1) / tile_w;
+  K->tiles_y = (p.out_h + tile_h - 1) / tile_h;
+  K->n_sensors = rig->n;
+  K->n_scales = p.n_scales;
+  K->order = p.order;
+  K->src_kind = src_kind;
+  K->gamma = (float)R.gamma;
+  K->tau_inv = (float)R.tau_inv;
+  K->tau_fp64 = (float)R.tau_fp64;
+  K->use_fp64 = (p.flags & LPA_FLAG_NO_FP64_FALLBACK) ? 0 : 1;
+  K->rgb = out->rgb;
+  K->rgb_pitch = out->row_pitch_bytes;
+  K->map = out->scale_map;
+  K->map_pitch = out->scale_map_pitch;
+  K->sd = out->sd_map;
+  K->sd_pitch = out->sd_map_pitch;
+  K->need_var = (p.n_scales > 1 || out->sd_map) ? 1 : 0;
+
+  for (int m = 0; m < p.n_scales; ++m) {
+    for (int cls = 0; cls < 2; ++cls) {
+      const double kappa = cls == 1 ? p.green_ratio : 1.0;
+      const double r = p.radii[m] * kappa;
+      const double h = R.h[m] * kappa * kappa;
+      const double cs = std::ldexp(1.0, -(int)std::ceil(std::log2(r)));
+      K->sc[m].radius[cls] = r;
+      K->sc[m].coord_scale[cls] = (float)cs;
+      K->sc[m].k_exp[cls] = (float)(-1.4426950408889634 / (h * cs * cs));
+      K->sc[m].e_edge[cls] = (float)std::exp(-r * r / h);
+    }
+  }
+  int lds = 0;
+  const double* O = p.out_affine;  // output map
+  for (int s = 0; s < rig->n; ++s) {
+    SensorK& S = K->s[s];
+    S = rig->k[s];
+    S.src = srcs[s];
+    S.pitch = pitches[s];
+    double wmx = 0, wmy = 0;
+    for (int cls = 0; cls < 2; ++cls) {
+      for (int m = 0; m < p.n_scales; ++m) {
+        const double wx = K->sc[m].radius[cls] * S.rownorm[0];
+        const double wy = K->sc[m].radius[cls] * S.rownorm[1];
+        const double nx = std::max(1.0, std::ceil(wx - 1e-9));
+        const double ny = std::max(1.0, std::ceil(wy - 1e-9));
+        if (nx > 120 || ny > 120)
+          return set_error(LPA_ERR_UNSUPPORTED, "window radius %g spans more than 240 sensor pixels",
+                           K->sc[m].radius[cls]);
+        S.nbox[cls][m][0] = (int8_t)nx;
+        S.nbox[cls][m][1] = (int8_t)ny;
+        wmx = std::max(wmx, wx);
+        wmy = std::max(wmy, wy);
+      }
+    }
+    S.wmax[0] = wmx;
+    S.wmax[1] = wmy;
+    // Every output pixel lies in the hull of the grid's corners; their sensor
+    // coordinates must stay well inside int range for the kernels' indexing.
+    for (int c = 0; c < 4; ++c) {
+      const double u = (c & 1) ? p.out_w - 1 : 0, v = (c & 2) ? p.out_h - 1 : 0;
+      const double X = O[0] * u + O[1] * v + O[2], Y = O[3] * u + O[4] * v + O[5];
+      const double px = S.inv[0] * X + S.inv[1] * Y + S.inv[2];
+      const double py = S.inv[3] * X + S.inv[4] * Y + S.inv[5];
+      if (!(std::fabs(px) < 1e8) || !(std::fabs(py) < 1e8))
+        return set_error(LPA_ERR_INVALID_ARG, "output grid maps %g px away from sensor %d", std::fmax(std::fabs(px), std::fabs(py)), s);
+    }
+    const double L00 = S.inv[0] * O[0] + S.inv[1] * O[3], L01 = S.inv[0] * O[1] + S.inv[1] * O[4];
+    const double L10 = S.inv[3] * O[0] + S.inv[4] * O[3], L11 = S.inv[3] * O[1] + S.inv[4] * O[4];
+    const double ex = std::fabs(L00) * (tile_w - 1) + std::fabs(L01) * (tile_h - 1);
+    const double ey = std::fabs(L10) * (tile_w - 1) + std::fabs(L11) * (tile_h - 1);
+    S.reg_w = (int)std::ceil(ex + 2 * wmx) + 8;
+    S.reg_h = (int)std::ceil(ey + 2 * wmy) + 8;
+    S.lds_off = lds;
+    lds += S.reg_w * S.reg_h;
+    if ((int64_t)lds * 8 > lpa_k_fit_max_lds_bytes())
+      return set_error(LPA_ERR_UNSUPPORTED, "tile %dx%d needs more than %d bytes of LDS", tile_w, tile_h,
+                       lpa_k_fit_max_lds_bytes());
+  }
+  K->lds_floats2 = lds;
+  return LPA_OK;
+}
+
+// Tile shapes tried in order (largest first) when a tile's LDS does not fit.
+static const int kTileShapes[][2] = {{16, 16}, {16, 8}, {8, 8}, {8, 4}, {4, 4}};
+
+lpa_status build_launch_fit(const lpa_rig* rig, const Resolved& R, const lpa_output* out, int src_kind,
+                            const void* const* srcs, const int64_t* pitches, int pref_w, int pref_h,
+                            LaunchK* K) {
+  lpa_status st = build_launch(rig, R, out, src_kind, srcs, pitches, pref_w, pref_h, K);
+  if (st != LPA_ERR_UNSUPPORTED) return st;
+  for (const auto& t : kTileShapes) {
+    if (t[0] * t[1] >= pref_w * pref_h) continue;
+    st = build_launch(rig, R, out, src_kind, srcs, pitches, t[0], t[1], K);
+    if (st != LPA_ERR_UNSUPPORTED) return st;
+  }
+  return st;
+}
+
+lpa_status check_ctx(lpa_ctx* ctx) {
+  if (!ctx) return set_error(LPA_ERR_INVALID_ARG, "context is NULL");
+  if (ctx->failed.load()) return set_error(LPA_ERR_DEVICE, "context failed after an earlier device error");
+  return LPA_OK;
+}
+
+// Scratch planes for the pre-pass forms, stream-ordered (hipMallocAsync).
+lpa_status alloc_async(lpa_ctx* ctx, size_t bytes, hipStream_t st, void** p) {
+  size_t used = ctx->used.fetch_add(bytes) + bytes;
+  if (used > ctx->budget) {
+    ctx->used.fetch_sub(bytes);
+    return set_error(LPA_ERR_OOM, "HBM budget of %zu bytes exceeded", ctx->budget);
+  }
+  hipError_t e = hipMallocAsync(p, bytes, st);
+  if (e != hipSuccess) {
+    ctx->used.fetch_sub(bytes);
+    (void)hipGetLastError();
+    return set_error(LPA_ERR_OOM, "hipMallocAsync(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  return LPA_OK;
+}
+
+void free_async(lpa_ctx* ctx, void* p, size_t bytes, hipStream_t st) {
+  if (!p) return;
+  (void)hipFreeAsync(p, st);
+  ctx->used.fetch_sub(bytes);
+}
+
+// Pre-pass every sensor into planes; fills srcs/pitches and the allocations.
+lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_t st, void** planes,
+                       size_t* plane_bytes, const void** srcs, int64_t* pitches) {
+  lpa_ctx* ctx = rig->ctx;
+  for (int s = 0; s < rig->n; ++s) {
+    const SensorK& S = rig->k[s];
+    const int64_t pitch = ((int64_t)S.width * (to_f16 ? 2 : 8) + 255) / 256 * 256;
+    plane_bytes[s] = (size_t)pitch * S.height;
+    lpa_status rs = alloc_async(ctx, plane_bytes[s], st, &planes[s]);
+    if (rs != LPA_OK) return rs;
+    const float enc = std::ldexp(1.0f, -rig->desc[s].bit_depth);
+    if (lpa_k_prepass(&S, f->dtype == LPA_DTYPE_F32, f->raw[s], f->row_pitch_bytes[s], planes[s], pitch,
+                      to_f16 ? 1 : 0, enc, st) != 0)
+      return device_error(ctx, hipGetLastError(), "pre-pass launch");
+    srcs[s] = planes[s];
+    pitches[s] = pitch;
+  }
+  return LPA_OK;
+}
+
+lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
+                            const lpa_output* out, void* stream, bool plain) {
+  if (!rig) return set_error(LPA_ERR_INVALID_ARG, "rig is NULL");
+  lpa_ctx* ctx = rig->ctx;
+  lpa_status st = check_ctx(ctx);
+  if (st != LPA_OK) return st;
+  Resolved R;
+  if ((st = resolve_params(params, &R)) != LPA_OK) return st;
+  if ((st = validate_frame(rig, frame, true)) != LPA_OK) return st;
+  if ((st = validate_output(params, out)) != LPA_OK) return st;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return device_error(ctx, e, "hipSetDevice");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+
+  const int storage = plain ? LPA_STORE_FP32 : R.p.storage;
+  int src_kind;
+  const void* srcs[LPA_MAX_SENSORS];
+  int64_t pitches[LPA_MAX_SENSORS];
+  void* planes[LPA_MAX_SENSORS] = {nullptr};
+  size_t plane_bytes[LPA_MAX_SENSORS] = {0};
+  int tw = 16, th = 16;
+
+  // Descriptor first: its validation must not leave work enqueued.
+  if (storage == LPA_STORE_FUSED) {
+    src_kind = frame->dtype == LPA_DTYPE_U16 ? SRC_RAW_U16 : SRC_RAW_F32;
+    for (int s = 0; s < rig->n; ++s) {
+      srcs[s] = frame->raw[s];
+      pitches[s] = frame->row_pitch_bytes[s];
+    }
+  } else {
+    src_kind = storage == LPA_STORE_FP16 ? SRC_PLANE_F16 : SRC_PLANE_F32;
+    for (int s = 0; s < rig->n; ++s) {
+      srcs[s] = nullptr;
+      pitches[s] = 0;
+    }
+  }
+  if (!plain) ctx->tuner.choose(Tuner::key_of(rig, R, src_kind), &tw, &th);
+  LaunchK K;
+  st = plain ? build_launch(rig, R, out, src_kind, srcs, pitches, 16, 16, &K)
+             : build_launch_fit(rig, R, out, src_kind, srcs, pitches, tw, th, &K);
+  if (st != LPA_OK) return st;
+
+  if (storage != LPA_STORE_FUSED) {
+    st = run_prepass(rig, frame, storage == LPA_STORE_FP16, hs, planes, plane_bytes, srcs, pitches);
+    if (st == LPA_OK)
+      for (int s = 0; s < rig->n; ++s) {
+        K.s[s].src = srcs[s];
+        K.s[s].pitch = pitches[s];
+      }
+  }
+  if (st == LPA_OK && lpa_k_fit(&K, hs) != 0) st = device_error(ctx, hipGetLastError(), "fit launch");
+  for (int s = 0; s < rig->n; ++s) free_async(ctx, planes[s], plane_bytes[s], hs);
+  return st;
+}
+
+}  // namespace lpa
+
+using namespace lpa;
+
+extern "C" {
+
+const char* lpa_last_error(void) { return g_last_error; }
+
+lpa_status lpa_create_ctx(int device, size_t hbm_budget_bytes, lpa_ctx** out) {
+  if (!out) return set_error(LPA_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return set_error(LPA_ERR_DEVICE, "no HIP device: %s", hipGetErrorString(e));
+  if (device < 0 || device >= n) return set_error(LPA_ERR_INVALID_ARG, "device %d outside 0..%d", device, n - 1);
+  if ((e = hipSetDevice(device)) != hipSuccess) return set_error(LPA_ERR_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  lpa_ctx* ctx = new (std::nothrow) lpa_ctx();
+  if (!ctx) return set_error(LPA_ERR_OOM, "host allocation failed");
+  ctx->device = device;
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) {
+    delete ctx;
+    return set_error(LPA_ERR_DEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+  }
+  ctx->n_cu = prop.multiProcessorCount;
+  size_t free_b = 0, total_b = 0;
+  (void)hipMemGetInfo(&free_b, &total_b);
+  ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+  lpa_status st = ctx_init_runtime(ctx);
+  if (st != LPA_OK) {
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return LPA_OK;
+}
+
+lpa_status lpa_destroy_ctx(lpa_ctx* ctx) {
+  if (!ctx) return set_error(LPA_ERR_INVALID_ARG, "context is NULL");
+  ctx_shutdown_runtime(ctx);
+  delete ctx;
+  return LPA_OK;
+}
+
+lpa_status lpa_create_rig(lpa_ctx* ctx, const lpa_rig_desc* desc, lpa_rig** out) {
+  lpa_status st = check_ctx(ctx);
+  if (st != LPA_OK) return st;
+  if (!out) return set_error(LPA_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if ((st = validate_rig(desc)) != LPA_OK) return st;
+  lpa_rig* rig = new (std::nothrow) lpa_rig();
+  if (!rig) return set_error(LPA_ERR_OOM, "host allocation failed");
+  rig->ctx = ctx;
+  rig->n = desc->n_sensors;
+  for (int s = 0; s < rig->n; ++s) {
+    rig->desc[s] = desc->sensors[s];
+    rig_constants(rig->desc[s], &rig->k[s]);
+  }
+  // Device-resident copy of the calibration / noise constants.
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMalloc(&rig->d_k, sizeof(SensorK) * rig->n);
+  if (e == hipSuccess) e = hipMemcpy(rig->d_k, rig->k, sizeof(SensorK) * rig->n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (rig->d_k) (void)hipFree(rig->d_k);
+    delete rig;
+    return device_error(ctx, e, "rig tables");
+  }
+  *out = rig;
+  return LPA_OK;
+}
+
+lpa_status lpa_destroy_rig(lpa_rig* rig) {
+  if (!rig) return set_error(LPA_ERR_INVALID_ARG, "rig is NULL");
+  if (rig->d_k) {
+    (void)hipSetDevice(rig->ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(rig->d_k);
+  }
+  delete rig;
+  return LPA_OK;
+}
+
+lpa_status lpa_reconstruct(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
+                           const lpa_output* out, void* hip_stream) {
+  try {
+    return reconstruct_impl(rig, frame, params, out, hip_stream, false);
+  } catch (...) {
+    return set_error(LPA_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+lpa_status lpa_reconstruct_plain(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
+                                 const lpa_output* out, void* hip_stream) {
+  try {
+    return reconstruct_impl(rig, frame, params, out, hip_stream, true);
+  } catch (...) {
+    return set_error(LPA_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+}  // extern "C"

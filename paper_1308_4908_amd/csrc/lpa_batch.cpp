@@ -1,0 +1,220 @@
+// lpa_batch.cpp -- batched reconstruction (one persistent launch over many
+// frames, recorded into a HIP graph and replayed), the tile autotuner, and the
+// context runtime set-up.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "lpa_host.hpp"
+
+namespace lpa {
+
+TuneKey Tuner::key_of(const lpa_rig* rig, const Resolved& R, int src_kind) {
+  TuneKey k;
+  k.order = R.p.order;
+  k.n_scales = R.p.n_scales;
+  k.n_sensors = rig->n;
+  k.src_kind = src_kind;
+  k.radius_q = (int)std::lround(R.p.radii[R.p.n_scales - 1] * 8.0);
+  const double* O = R.p.out_affine;
+  const double* A = rig->desc[0].affine;
+  const double zo = std::sqrt(std::fabs(O[0] * O[4] - O[1] * O[3]));
+  const double za = std::sqrt(std::fabs(A[0] * A[4] - A[1] * A[3]));
+  k.zoom_q = (int)std::lround(16.0 * zo / za);
+  return k;
+}
+
+static int src_kind_of(const lpa_params& p, const lpa_frame& f) {
+  if (p.storage == LPA_STORE_FUSED) return f.dtype == LPA_DTYPE_U16 ? SRC_RAW_U16 : SRC_RAW_F32;
+  return p.storage == LPA_STORE_FP16 ? SRC_PLANE_F16 : SRC_PLANE_F32;
+}
+
+lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_frame* frames,
+                          const lpa_params* params, const lpa_output* outs, hipStream_t stream,
+                          std::vector<LaunchK>* ks, int* src_kind, std::vector<PlaneAlloc>* planes) {
+  ks->assign(n, LaunchK());
+  int sk = -1;
+  std::vector<Resolved> Rs(n);
+  for (int i = 0; i < n; ++i) {
+    if (!rigs[i] || rigs[i]->ctx != ctx) return set_error(LPA_ERR_INVALID_ARG, "frame %d: rig missing or from another context", i);
+    lpa_status st = resolve_params(&params[i], &Rs[i]);
+    if (st == LPA_OK) st = validate_frame(rigs[i], &frames[i], true);
+    if (st == LPA_OK) st = validate_output(&params[i], &outs[i]);
+    if (st != LPA_OK) return set_error(st, "frame %d: %s", i, g_last_error);
+    const int k = src_kind_of(params[i], frames[i]);
+    if (sk >= 0 && k != sk) return set_error(LPA_ERR_INVALID_ARG, "frames of one batch must share storage and dtype");
+    sk = k;
+  }
+  // descriptors (and their validation) before anything is enqueued
+  for (int i = 0; i < n; ++i) {
+    const void* srcs[LPA_MAX_SENSORS];
+    int64_t pitches[LPA_MAX_SENSORS];
+    for (int s = 0; s < rigs[i]->n; ++s) {
+      srcs[s] = frames[i].raw[s];
+      pitches[s] = frames[i].row_pitch_bytes[s];
+    }
+    int tw = 16, th = 16;
+    ctx->tuner.choose(Tuner::key_of(rigs[i], Rs[i], sk), &tw, &th);
+    lpa_status st = build_launch(rigs[i], Rs[i], &outs[i], sk, srcs, pitches, tw, th, &(*ks)[i]);
+    if (st == LPA_ERR_UNSUPPORTED && tw * th == 256)
+      for (const int* t : {(const int[]){16, 16}, (const int[]){32, 8}, (const int[]){64, 4}}) {
+        st = build_launch(rigs[i], Rs[i], &outs[i], sk, srcs, pitches, t[0], t[1], &(*ks)[i]);
+        if (st != LPA_ERR_UNSUPPORTED) break;
+      }
+    if (st != LPA_OK) return set_error(st, "frame %d: %s", i, g_last_error);
+  }
+  *src_kind = sk;
+  if (sk == SRC_PLANE_F32 || sk == SRC_PLANE_F16) {
+    for (int i = 0; i < n; ++i) {
+      void* pl[LPA_MAX_SENSORS] = {nullptr};
+      size_t pb[LPA_MAX_SENSORS] = {0};
+      const void* srcs[LPA_MAX_SENSORS];
+      int64_t pitches[LPA_MAX_SENSORS];
+      lpa_status st = run_prepass(rigs[i], &frames[i], sk == SRC_PLANE_F16, stream, pl, pb, srcs, pitches);
+      for (int s = 0; s < rigs[i]->n; ++s)
+        if (pl[s]) planes->push_back({pl[s], pb[s]});
+      if (st != LPA_OK) return st;
+      for (int s = 0; s < rigs[i]->n; ++s) {
+        (*ks)[i].s[s].src = srcs[s];
+        (*ks)[i].s[s].pitch = pitches[s];
+      }
+    }
+  }
+  return LPA_OK;
+}
+
+static void slot_release(BatchSlot& sl) {
+  if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+  if (sl.h_buf) (void)hipHostFree(sl.h_buf);
+  if (sl.d_buf) (void)hipFree(sl.d_buf);
+  sl.exec = nullptr;
+  sl.h_buf = nullptr;
+  sl.d_buf = nullptr;
+  sl.cap = 0;
+}
+
+lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, hipStream_t stream) {
+  const int n = (int)ks.size();
+  int block = ks[0].tile_w * ks[0].tile_h;
+  int lds = 0;
+  int64_t total = 0;
+  for (const LaunchK& K : ks) {
+    if (K.tile_w * K.tile_h != block) return set_error(LPA_ERR_INTERNAL, "batch tiles differ in lane count");
+    lds = std::max(lds, K.lds_floats2);
+    total += (int64_t)K.tiles_x * K.tiles_y;
+  }
+  if (total > (int64_t)INT32_MAX) return set_error(LPA_ERR_UNSUPPORTED, "batch exceeds 2^31 tiles");
+  const int grid = (int)std::min<int64_t>(total, (int64_t)ctx->n_cu * 4);
+
+  std::lock_guard<std::mutex> g(ctx->batch_mu);
+  BatchSlot& sl = ctx->slots[ctx->next_slot];
+  ctx->next_slot = (ctx->next_slot + 1) % (int)ctx->slots.size();
+  hipError_t e;
+  if (sl.used && (e = hipEventSynchronize(sl.done)) != hipSuccess) return device_error(ctx, e, "batch slot wait");
+  if (sl.cap < n) {
+    slot_release(sl);
+    int cap = 64;
+    while (cap < n) cap *= 2;
+    BatchLayout L(cap);
+    if ((e = hipHostMalloc(&sl.h_buf, L.copy_bytes, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipMalloc(&sl.d_buf, L.total_bytes)) != hipSuccess) {
+      slot_release(sl);
+      return set_error(LPA_ERR_OOM, "batch table allocation: %s", hipGetErrorString(e));
+    }
+    sl.cap = cap;
+  }
+  BatchLayout L(sl.cap);
+  char* h = static_cast<char*>(sl.h_buf);
+  BatchHeader hdr;
+  hdr.n_frames = n;
+  hdr.pad_ = 0;
+  hdr.total_tiles = total;
+  std::memcpy(h, &hdr, sizeof(hdr));
+  std::memcpy(h + L.frames_off, ks.data(), sizeof(LaunchK) * n);
+  int64_t* first = reinterpret_cast<int64_t*>(h + L.first_off);
+  int64_t acc = 0;
+  for (int i = 0; i < n; ++i) {
+    first[i] = acc;
+    acc += (int64_t)ks[i].tiles_x * ks[i].tiles_y;
+  }
+  const int64_t sig[5] = {src_kind, block, lds, grid, sl.cap};
+  if (!sl.exec || std::memcmp(sig, sl.sig, sizeof(sig)) != 0) {
+    if (sl.exec) {
+      (void)hipGraphExecDestroy(sl.exec);
+      sl.exec = nullptr;
+    }
+    char* d = static_cast<char*>(sl.d_buf);
+    hipGraph_t graph = nullptr;
+    if ((e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return device_error(ctx, e, "begin capture");
+    (void)hipMemcpyAsync(d, h, L.copy_bytes, hipMemcpyHostToDevice, ctx->capture_stream);
+    int32_t* q = reinterpret_cast<int32_t*>(d + L.queue_off);
+    (void)lpa_k_zero_i32(q, 1, ctx->capture_stream);
+    (void)lpa_k_fit_batch(reinterpret_cast<const BatchHeader*>(d), reinterpret_cast<const LaunchK*>(d + L.frames_off),
+                          reinterpret_cast<const int64_t*>(d + L.first_off), q, src_kind, block, lds, grid,
+                          ctx->capture_stream);
+    if ((e = hipStreamEndCapture(ctx->capture_stream, &graph)) != hipSuccess) return device_error(ctx, e, "end capture");
+    e = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      sl.exec = nullptr;
+      return device_error(ctx, e, "graph instantiate");
+    }
+    std::memcpy(sl.sig, sig, sizeof(sig));
+  }
+  if ((e = hipGraphLaunch(sl.exec, stream)) != hipSuccess) return device_error(ctx, e, "graph launch");
+  if ((e = hipEventRecord(sl.done, stream)) != hipSuccess) return device_error(ctx, e, "event record");
+  sl.used = true;
+  return LPA_OK;
+}
+
+lpa_status ctx_init_runtime(lpa_ctx* ctx) {
+  hipError_t e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return set_error(LPA_ERR_DEVICE, "stream create: %s", hipGetErrorString(e));
+  ctx->slots.resize(4);
+  for (BatchSlot& sl : ctx->slots)
+    if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess)
+      return set_error(LPA_ERR_DEVICE, "event create: %s", hipGetErrorString(e));
+  return serve_init(ctx);
+}
+
+void ctx_shutdown_runtime(lpa_ctx* ctx) {
+  serve_shutdown(ctx);
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (BatchSlot& sl : ctx->slots) {
+    slot_release(sl);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+  }
+  ctx->slots.clear();
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+  ctx->capture_stream = nullptr;
+}
+
+}  // namespace lpa
+
+using namespace lpa;
+
+extern "C" lpa_status lpa_reconstruct_batch(lpa_ctx* ctx, int32_t n, lpa_rig* const* rigs,
+                                            const lpa_frame* frames, const lpa_params* params,
+                                            const lpa_output* outs, void* hip_stream) {
+  try {
+    lpa_status st = check_ctx(ctx);
+    if (st != LPA_OK) return st;
+    if (n < 1 || n > 4096 || !rigs || !frames || !params || !outs)
+      return set_error(LPA_ERR_INVALID_ARG, "batch needs 1..4096 frames and non-NULL arrays");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return device_error(ctx, e, "hipSetDevice");
+    hipStream_t hs = static_cast<hipStream_t>(hip_stream);
+    std::vector<LaunchK> ks;
+    std::vector<PlaneAlloc> planes;
+    int sk = 0;
+    st = prepare_frames(ctx, n, rigs, frames, params, outs, hs, &ks, &sk, &planes);
+    if (st == LPA_OK) st = launch_batch(ctx, ks, sk, hs);
+    for (const PlaneAlloc& p : planes) free_async(ctx, p.p, p.bytes, hs);
+    return st;
+  } catch (...) {
+    return set_error(LPA_ERR_INTERNAL, "unexpected exception");
+  }
+}

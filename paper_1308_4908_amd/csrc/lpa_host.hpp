@@ -1,0 +1,186 @@
+// lpa_host.hpp -- host-side state behind the C ABI (contexts, rigs, the
+// autotuner and the serving scheduler).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/lpa.h"
+#include "lpa_internal.hpp"
+
+namespace lpa {
+
+struct Resolved {
+  lpa_params p;
+  double tau_inv, tau_fp64, gamma;
+  double h[LPA_MAX_SCALES];
+};
+
+// Class of a frame for tuning: everything that changes the kernel's cost per
+// pixel, nothing that depends on the frame's data.  A frame's tuning choice
+// depends only on its class, so its result does not depend on the other
+// frames it is launched with.
+struct TuneKey {
+  int order, n_scales, n_sensors, src_kind;
+  int radius_q;  // largest radius in 1/8 px
+  int zoom_q;    // output-to-sensor scale in 1/16
+  bool operator<(const TuneKey& o) const {
+    const int a[6] = {order, n_scales, n_sensors, src_kind, radius_q, zoom_q};
+    const int b[6] = {o.order, o.n_scales, o.n_sensors, o.src_kind, o.radius_q, o.zoom_q};
+    for (int i = 0; i < 6; ++i)
+      if (a[i] != b[i]) return a[i] < b[i];
+    return false;
+  }
+};
+
+struct TuneChoice {
+  int tile_w = 16, tile_h = 16;
+};
+
+struct lpa_rig_fwd;
+
+class Tuner {
+ public:
+  // Tile shape for a frame's class: the measured best if the class was tuned,
+  // else 16 x 16.  Every candidate has 256 lanes, so batched launches can mix
+  // classes.
+  void choose(const TuneKey& k, int* tw, int* th) {
+    TuneChoice c;
+    if (lookup(k, &c)) {
+      *tw = c.tile_w;
+      *th = c.tile_h;
+    } else {
+      *tw = 16;
+      *th = 16;
+    }
+  }
+  void set(const TuneKey& k, TuneChoice c) {
+    std::lock_guard<std::mutex> g(mu_);
+    table_[k] = c;
+  }
+  bool lookup(const TuneKey& k, TuneChoice* c) {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = table_.find(k);
+    if (it == table_.end()) return false;
+    *c = it->second;
+    return true;
+  }
+  static TuneKey key_of(const struct ::lpa_rig* rig, const Resolved& R, int src_kind);
+  size_t size() {
+    std::lock_guard<std::mutex> g(mu_);
+    return table_.size();
+  }
+  std::map<TuneKey, TuneChoice> snapshot() {
+    std::lock_guard<std::mutex> g(mu_);
+    return table_;
+  }
+
+ private:
+  std::mutex mu_;
+  std::map<TuneKey, TuneChoice> table_;
+};
+
+// One reusable batch table: pinned host staging, device copy, the captured
+// graph that copies it and runs the persistent kernel, and an event marking
+// the end of its last use.
+struct BatchSlot {
+  void* h_buf = nullptr;
+  void* d_buf = nullptr;
+  int cap = 0;
+  hipEvent_t done = nullptr;
+  bool used = false;
+  hipGraphExec_t exec = nullptr;
+  int64_t sig[5] = {0, 0, 0, 0, 0};
+};
+
+// Byte layout of a batch table of capacity cap.
+struct BatchLayout {
+  size_t frames_off, first_off, queue_off, copy_bytes, total_bytes;
+  explicit BatchLayout(int cap) {
+    frames_off = 256;
+    first_off = frames_off + sizeof(LaunchK) * (size_t)cap;
+    queue_off = (first_off + sizeof(int64_t) * (size_t)cap + 255) / 256 * 256;
+    copy_bytes = first_off + sizeof(int64_t) * (size_t)cap;
+    total_bytes = queue_off + 256;
+  }
+};
+
+struct Scheduler;  // lpa_serve.cpp
+
+}  // namespace lpa
+
+struct lpa_ctx {
+  int device = 0;
+  int n_cu = 256;
+  size_t budget = 0;
+  std::atomic<size_t> used{0};
+  std::atomic<bool> failed{false};
+  lpa::Tuner tuner;
+  // batch path: a ring of reusable tables and a stream used only for capture
+  std::mutex batch_mu;
+  std::vector<lpa::BatchSlot> slots;
+  int next_slot = 0;
+  hipStream_t capture_stream = nullptr;
+  // serving
+  lpa::Scheduler* sched = nullptr;
+};
+
+struct lpa_rig {
+  lpa_ctx* ctx = nullptr;
+  int n = 0;
+  lpa_sensor_desc desc[LPA_MAX_SENSORS];
+  lpa::SensorK k[LPA_MAX_SENSORS];  // host copy of the resident constants
+  lpa::SensorK* d_k = nullptr;       // device-resident constants
+};
+
+namespace lpa {
+
+extern thread_local char g_last_error[512];
+lpa_status set_error(lpa_status st, const char* fmt, ...);
+lpa_status device_error(lpa_ctx* ctx, hipError_t e, const char* what);
+lpa_status check_ctx(lpa_ctx* ctx);
+lpa_status resolve_params(const lpa_params* p, Resolved* r);
+lpa_status validate_frame(const lpa_rig* rig, const lpa_frame* f, bool need_device);
+lpa_status validate_output(const lpa_params* p, const lpa_output* o);
+lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output* out, int src_kind,
+                        const void* const* srcs, const int64_t* pitches, int tile_w, int tile_h,
+                        LaunchK* K);
+lpa_status build_launch_fit(const lpa_rig* rig, const Resolved& R, const lpa_output* out, int src_kind,
+                            const void* const* srcs, const int64_t* pitches, int pref_w, int pref_h,
+                            LaunchK* K);
+lpa_status alloc_async(lpa_ctx* ctx, size_t bytes, hipStream_t st, void** p);
+void free_async(lpa_ctx* ctx, void* p, size_t bytes, hipStream_t st);
+lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_t st, void** planes,
+                       size_t* plane_bytes, const void** srcs, int64_t* pitches);
+
+// Runtime pieces owned by a context (scheduler threads, batch tables).
+lpa_status ctx_init_runtime(lpa_ctx* ctx);
+void ctx_shutdown_runtime(lpa_ctx* ctx);
+
+// Launch a prepared batch (descriptors already built, planes already made) on
+// `stream` through a slot's captured graph.  Thread-safe.
+lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, hipStream_t stream);
+// Build descriptors for a list of frames (validating each) and run the
+// pre-pass where the storage form needs one; plane allocations are returned
+// for the caller to free (stream-ordered) after the launch.
+struct PlaneAlloc {
+  void* p;
+  size_t bytes;
+};
+lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_frame* frames,
+                          const lpa_params* params, const lpa_output* outs, hipStream_t stream,
+                          std::vector<LaunchK>* ks, int* src_kind, std::vector<PlaneAlloc>* planes);
+lpa_status serve_init(lpa_ctx* ctx);
+void serve_shutdown(lpa_ctx* ctx);
+
+}  // namespace lpa

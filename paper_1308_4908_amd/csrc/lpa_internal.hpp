@@ -1,0 +1,101 @@
+// lpa_internal.hpp -- launch descriptors shared by the host library and the
+// gfx950 kernels.  Everything a fit launch needs is precomputed on the host in
+// FP64 and packed here; the kernels read it through scalar loads.
+#pragma once
+
+#include <stdint.h>
+
+namespace lpa {
+
+constexpr int kMaxSensors = 8;
+constexpr int kMaxScales = 8;
+
+// Where the fit kernel reads samples from.
+enum SrcKind : int32_t {
+  SRC_RAW_U16 = 0,   // raw uint16 DN, decoded while staging (fused)
+  SRC_RAW_F32 = 1,   // raw float DN (test input), decoded while staging (fused)
+  SRC_PLANE_F32 = 2, // float2 (radiance, inverse variance) plane from a pre-pass
+  SRC_PLANE_F16 = 3, // half normalised radiance plane from a pre-pass (+Inf = masked)
+};
+
+// Per-sensor constants of one launch.
+struct SensorK {
+  double fwd[6];        // T_s: X = f0 x + f1 y + f2, Y = f3 x + f4 y + f5
+  double inv[6];        // T_s^-1
+  double wmax[2];       // largest box half-width (sensor px) along x, y over all scales/channels
+  double rownorm[2];    // |row 0|, |row 1| of the inverse linear part
+  const void* src;      // raw plane or pre-pass plane (device)
+  int64_t pitch;        // bytes between rows of src
+  float inv_ge;         // 1 / (g n)
+  float gain;           // g
+  float read_var;       // sigma_r^2 [DN^2]
+  float black;          // b [DN]
+  float sat;            // saturation [DN]
+  float norm_decode;    // 2^bit_depth (FP16 plane value -> y - b)
+  int32_t width, height;
+  int32_t reg_w, reg_h; // LDS region bound (samples) for the launch's tile shape
+  int32_t lds_off;      // region offset in the LDS sample array (float2 units)
+  int8_t sub_n[3];      // number of CFA sub-lattices of channel c (1 or 2)
+  int8_t sub_ox[3][2];  // sub-lattice column parity
+  int8_t sub_oy[3][2];  // sub-lattice row parity
+  int8_t nbox[2][kMaxScales][2]; // box size (sub-lattice points) [class][scale][x|y]
+  int8_t pad_[5];
+};
+
+// Per-scale constants, per channel class (0: R and B, 1: G).
+struct ScaleK {
+  double radius[2];   // r' = r * kappa_class
+  float coord_scale[2]; // power-of-two s with s * r' <= 1 (coordinates are scaled by s)
+  float k_exp[2];     // -log2(e) / (h' s^2): window exp2 argument per scaled |d|^2
+  float e_edge[2];    // exp(-r'^2 / h'): subtracted so the window vanishes at r'
+};
+
+struct LaunchK {
+  double out_affine[6];
+  int32_t out_w, out_h;
+  int32_t tiles_x, tiles_y; // tile grid of this frame
+  int32_t tile_w, tile_h;
+  int32_t n_sensors, n_scales;
+  int32_t order, src_kind;
+  float gamma, tau_inv, tau_fp64;
+  int32_t use_fp64;
+  int32_t lds_floats2;      // float2 elements of LDS this launch uses
+  int32_t need_var;         // estimator variance needed (several radii or an sd map)
+  float* rgb;
+  int64_t rgb_pitch;        // bytes
+  uint8_t* map;
+  int64_t map_pitch;        // bytes
+  float* sd;                // optional standard deviation of each output value
+  int64_t sd_pitch;         // bytes
+  SensorK s[kMaxSensors];
+  ScaleK sc[kMaxScales];
+};
+
+// Header of a batch table in device memory (read by the persistent kernel, so
+// a captured graph can be replayed with new table contents).
+struct BatchHeader {
+  int32_t n_frames;
+  int32_t pad_;
+  int64_t total_tiles;
+};
+
+}  // namespace lpa
+
+// Launchers implemented in lpa_kernels.hip (host-callable).
+extern "C" {
+// Pre-pass over one sensor: raw -> FP32 (radiance, inverse variance) plane or
+// FP16 normalised radiance plane.
+int lpa_k_prepass(const lpa::SensorK* s, int raw_is_f32, const void* raw, int64_t raw_pitch,
+                  void* plane, int64_t plane_pitch, int to_f16, float norm_encode, void* stream);
+// One fit launch over the whole tile grid of a frame.
+int lpa_k_fit(const lpa::LaunchK* k, void* stream);
+// One persistent launch over many frames.
+// All frames of one batch share src_kind; each frame's descriptor carries its tile shape
+// (block = tile_w * tile_h threads must be the same for all frames).
+int lpa_k_fit_batch(const lpa::BatchHeader* d_hdr, const lpa::LaunchK* d_frames,
+                    const int64_t* d_first_tile, int32_t* d_queue, int32_t src_kind, int32_t block,
+                    int32_t lds_floats2, int32_t grid, void* stream);
+int lpa_k_fit_max_lds_bytes(void);
+// Zero n ints with a small kernel (graph-safe replacement for a memset).
+int lpa_k_zero_i32(int32_t* p, int32_t n, void* stream);
+}

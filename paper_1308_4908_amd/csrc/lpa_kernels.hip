@@ -1,0 +1,675 @@
+// lpa_kernels.hip -- gfx950 kernels for LPA + ICI multi-sensor HDR
+// reconstruction (Kronander et al., arXiv 1308.4908).
+//
+// Work decomposition: one workgroup per output tile, one lane per output
+// pixel.  A workgroup first stages, for every sensor, the patch of samples its
+// tile can reach into LDS as (radiance, inverse variance) pairs: raw DN are
+// decoded there (Sec. 6 eq. Efsi, Sec. 6.1 eq. varianceestiamte, saturation
+// masking) or read from a pre-pass plane.  Each lane then walks, per colour
+// channel and window radius, the CFA sub-lattice points of every sensor inside
+// the radius' bounding box, accumulates the weighted moments of the local
+// polynomial model (Sec. 5.1, eq. wlsqe) in FP32, solves the 1x1/3x3/6x6
+// normal equations in registers (LDL^T of the Jacobi-equilibrated matrix; an
+// FP64 re-solve when an order-2 pivot is small) and runs ICI across radii.
+//
+// The normal matrix of a polynomial basis has Hankel structure: entry (i, j)
+// is the weighted moment of the monomial phi_i phi_j, so an order-2 fit needs
+// 15 distinct moments (not 21) and its variance matrix 15 more.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lpa_internal.hpp"
+
+namespace lpa {
+
+// ---------------------------------------------------------------------------
+// Polynomial basis bookkeeping.  Monomials x^p y^q with p + q <= 4 are
+// numbered by degree, then by decreasing power of x.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int midx(int p, int q) { return (p + q) * (p + q + 1) / 2 + q; }
+template <int ORDER>
+__host__ __device__ constexpr int n_basis() { return ORDER == 0 ? 1 : (ORDER == 1 ? 3 : 6); }
+template <int ORDER>
+__host__ __device__ constexpr int n_mom() { return ORDER == 0 ? 1 : (ORDER == 1 ? 6 : 15); }
+// exponents of basis function i: [1, x, y, x^2, x y, y^2]
+__host__ __device__ constexpr int bp(int i) { return i == 1 ? 1 : i == 3 ? 2 : i == 4 ? 1 : 0; }
+__host__ __device__ constexpr int bq(int i) { return i == 2 ? 1 : i == 4 ? 1 : i == 5 ? 2 : 0; }
+__host__ __device__ constexpr int aidx(int i, int j) { return midx(bp(i) + bp(j), bq(i) + bq(j)); }
+
+template <int ORDER, bool ICI>
+struct Acc {
+  float m[n_mom<ORDER>()];            // sum w * monomial
+  float b[n_basis<ORDER>()];          // sum w * f * phi
+  float B[ICI ? n_mom<ORDER>() : 1];  // sum K w * monomial (variance of C0)
+  int n;                              // samples with positive weight
+};
+
+template <int ORDER, bool ICI>
+__device__ __forceinline__ void acc_zero(Acc<ORDER, ICI>& a) {
+#pragma unroll
+  for (int k = 0; k < n_mom<ORDER>(); ++k) a.m[k] = 0.f;
+#pragma unroll
+  for (int k = 0; k < n_basis<ORDER>(); ++k) a.b[k] = 0.f;
+#pragma unroll
+  for (int k = 0; k < (ICI ? n_mom<ORDER>() : 1); ++k) a.B[k] = 0.f;
+  a.n = 0;
+}
+
+// One sample: scaled offset (dx, dy), radiance f, inverse variance iv.
+template <int ORDER, bool ICI>
+__device__ __forceinline__ void acc_sample(Acc<ORDER, ICI>& a, float dx, float dy, float f, float iv,
+                                           float k_exp, float e_edge) {
+  float mono[n_mom<ORDER>()];
+  mono[0] = 1.f;
+  float r2;
+  if constexpr (ORDER >= 1) {
+    mono[1] = dx;
+    mono[2] = dy;
+    mono[3] = dx * dx;
+    mono[4] = dx * dy;
+    mono[5] = dy * dy;
+    r2 = mono[3] + mono[5];
+  } else {
+    r2 = __builtin_fmaf(dx, dx, dy * dy);
+  }
+  if constexpr (ORDER >= 2) {
+    mono[6] = mono[3] * dx;
+    mono[7] = mono[3] * dy;
+    mono[8] = mono[4] * dy;
+    mono[9] = mono[5] * dy;
+    mono[10] = mono[3] * mono[3];
+    mono[11] = mono[6] * dy;
+    mono[12] = mono[3] * mono[5];
+    mono[13] = mono[8] * dy;
+    mono[14] = mono[5] * mono[5];
+  }
+  // Gaussian window shifted to vanish at the radius; zero outside the disc.
+  const float kw = fmaxf(__builtin_amdgcn_exp2f(r2 * k_exp) - e_edge, 0.f);
+  const float w = kw * iv;
+  a.n += (w > 0.f) ? 1 : 0;
+  const float wf = w * f;
+  a.m[0] += w;
+#pragma unroll
+  for (int k = 1; k < n_mom<ORDER>(); ++k) a.m[k] = __builtin_fmaf(w, mono[k], a.m[k]);
+  a.b[0] += wf;
+#pragma unroll
+  for (int k = 1; k < n_basis<ORDER>(); ++k) a.b[k] = __builtin_fmaf(wf, mono[k], a.b[k]);
+  if constexpr (ICI) {
+    const float w2 = w * kw;
+    a.B[0] += w2;
+#pragma unroll
+    for (int k = 1; k < n_mom<ORDER>(); ++k) a.B[k] = __builtin_fmaf(w2, mono[k], a.B[k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident solve.  LDL^T of the Jacobi-equilibrated normal matrix
+// A~ = S A S (S = diag(A)^-1/2); its leading blocks are the factorizations of
+// the order-1 and order-0 fits, so one factorization serves every order.
+// For order o: rho_o = smallest pivot among the first n_o, valid iff the
+// support has >= n_o samples and rho_o >= tau; g = A^-1 e0 = s0 S A~^-1 e0,
+// C0 = g . b and var(C0) = g^T B g.
+// ---------------------------------------------------------------------------
+template <typename T, int ORDER>
+struct Fits {
+  T y[ORDER + 1];
+  T v[ORDER + 1];
+  T rho[ORDER + 1];
+  bool ok[ORDER + 1];
+  T g[ORDER + 1][n_basis<ORDER>()];  // A^-1 e0 of each order (C0 = g . b)
+};
+
+template <typename T>
+__device__ __forceinline__ T rsqrt_t(T x);
+template <>
+__device__ __forceinline__ float rsqrt_t<float>(float x) { return __frsqrt_rn(x); }
+template <>
+__device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
+
+template <typename T, int ORDER, bool ICI>
+__device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, int n, T tau,
+                                           Fits<T, ORDER>& out) {
+  constexpr int NB = n_basis<ORDER>();
+  T s[NB];
+  bool dok[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const T aii = m[aidx(i, i)];
+    dok[i] = aii > T(0);
+    s[i] = dok[i] ? rsqrt_t<T>(aii) : T(0);
+  }
+  T L[NB][NB];
+  T D[NB], iD[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    T d = s[j] * s[j] * m[aidx(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k] * D[k];
+    D[j] = d;
+    iD[j] = d > T(0) ? T(1) / d : T(0);
+#pragma unroll
+    for (int i = j + 1; i < NB; ++i) {
+      T t = s[i] * s[j] * m[aidx(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k] * D[k];
+      L[i][j] = t * iD[j];
+    }
+  }
+  // forward substitution of e0 is shared by all orders
+  T z[NB];
+  z[0] = T(1);
+#pragma unroll
+  for (int i = 1; i < NB; ++i) {
+    T t = T(0);
+#pragma unroll
+    for (int k = 0; k < i; ++k) t -= L[i][k] * z[k];
+    z[i] = t;
+  }
+  T rho = T(3.0e38);
+  bool diag_all = true;
+#pragma unroll
+  for (int o = 0; o <= ORDER; ++o) {
+    constexpr int nb_tab[3] = {1, 3, 6};
+    const int no = nb_tab[o];
+#pragma unroll
+    for (int i = (o == 0 ? 0 : nb_tab[o - 1]); i < no; ++i) {
+      rho = D[i] < rho ? D[i] : rho;
+      diag_all = diag_all && dok[i];
+    }
+    T x[NB];
+#pragma unroll
+    for (int i = NB - 1; i >= 0; --i) {
+      if (i < no) {
+        T t = z[i] * iD[i];
+#pragma unroll
+        for (int k = i + 1; k < NB; ++k)
+          if (k < no) t -= L[k][i] * x[k];
+        x[i] = t;
+      }
+    }
+    T g[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) g[i] = (i < no) ? s[0] * s[i] * x[i] : T(0);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) out.g[o][i] = g[i];
+    T y = T(0);
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+      if (i < no) y += g[i] * b[i];
+    T v = T(0);
+    if constexpr (ICI) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        if (i < no) {
+          T t = g[i] * B[aidx(i, i)];
+#pragma unroll
+          for (int j = i + 1; j < NB; ++j)
+            if (j < no) t += T(2) * g[j] * B[aidx(i, j)];
+          v += g[i] * t;
+        }
+      }
+    }
+    out.y[o] = y;
+    out.v[o] = v;
+    out.rho[o] = (diag_all && rho > T(0)) ? rho : T(0);
+    out.ok[o] = diag_all && (rho >= tau) && (n >= no);
+  }
+}
+
+// ICI running state of one order (reading: Goldenshluger-Nemirovski rule).
+struct IciState {
+  float lo, hi, y, sd;
+  int chosen;
+  bool stopped, any;
+};
+
+__device__ __forceinline__ void ici_init(IciState& st) {
+  st.lo = -__builtin_inff();
+  st.hi = __builtin_inff();
+  st.y = __builtin_nanf("");
+  st.sd = __builtin_nanf("");
+  st.chosen = -1;
+  st.stopped = false;
+  st.any = false;
+}
+
+__device__ __forceinline__ void ici_step(IciState& st, bool ok, float y, float v, float gamma, int m) {
+  if (!ok) return;
+  st.any = true;
+  if (st.stopped) return;
+  const float sd = sqrtf(fmaxf(v, 0.f));
+  st.lo = fmaxf(st.lo, y - gamma * sd);
+  st.hi = fminf(st.hi, y + gamma * sd);
+  if (st.lo <= st.hi) {
+    st.chosen = m;
+    st.y = y;
+    st.sd = sd;
+  } else {
+    st.stopped = true;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sample decode (Sec. 6 eq. Efsi, Sec. 6.1 eq. varianceestiamte): radiance
+// f = (y - b) / (g n), variance (g (y - b)_+ + Var r) / (g n)^2; masked
+// (y >= saturation or outside the sensor) -> (0, 0).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 decode_dn(const SensorK& S, float y) {
+  if (!(y < S.sat)) return make_float2(0.f, 0.f);
+  const float yb = y - S.black;
+  const float var = __builtin_fmaf(S.gain, fmaxf(yb, 0.f), S.read_var) * (S.inv_ge * S.inv_ge);
+  return make_float2(yb * S.inv_ge, 1.f / var);
+}
+
+__device__ __forceinline__ float2 decode_f16(const SensorK& S, __half h) {
+  const float v = __half2float(h);
+  if (__builtin_isinf(v)) return make_float2(0.f, 0.f);
+  const float yb = v * S.norm_decode;  // exact: power-of-two scale
+  const float var = __builtin_fmaf(S.gain, fmaxf(yb, 0.f), S.read_var) * (S.inv_ge * S.inv_ge);
+  return make_float2(yb * S.inv_ge, 1.f / var);
+}
+
+template <int SRC>
+__device__ __forceinline__ float2 load_sample(const SensorK& S, int x, int y) {
+  if (x < 0 || y < 0 || x >= S.width || y >= S.height) return make_float2(0.f, 0.f);
+  const char* row = static_cast<const char*>(S.src) + (int64_t)y * S.pitch;
+  if constexpr (SRC == SRC_RAW_U16) {
+    return decode_dn(S, (float)reinterpret_cast<const uint16_t*>(row)[x]);
+  } else if constexpr (SRC == SRC_RAW_F32) {
+    return decode_dn(S, reinterpret_cast<const float*>(row)[x]);
+  } else if constexpr (SRC == SRC_PLANE_F32) {
+    return reinterpret_cast<const float2*>(row)[x];
+  } else {
+    return decode_f16(S, reinterpret_cast<const __half*>(row)[x]);
+  }
+}
+
+// Region of sensor s staged for the tile at output origin (u0, v0).
+struct Region {
+  int x0, y0, w, h;
+};
+
+__device__ __forceinline__ Region tile_region(const LaunchK& K, const SensorK& S, int u0, int v0) {
+  double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double u = u0 + ((c & 1) ? K.tile_w - 1 : 0);
+    const double v = v0 + ((c & 2) ? K.tile_h - 1 : 0);
+    const double X = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
+    const double Y = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
+    const double px = S.inv[0] * X + S.inv[1] * Y + S.inv[2];
+    const double py = S.inv[3] * X + S.inv[4] * Y + S.inv[5];
+    mnx = fmin(mnx, px);
+    mxx = fmax(mxx, px);
+    mny = fmin(mny, py);
+    mxy = fmax(mxy, py);
+  }
+  Region r;
+  r.x0 = (int)floor(mnx - S.wmax[0]) - 1;
+  r.y0 = (int)floor(mny - S.wmax[1]) - 1;
+  r.w = min((int)ceil(mxx + S.wmax[0]) + 3 - r.x0 + 1, S.reg_w);
+  r.h = min((int)ceil(mxy + S.wmax[1]) + 3 - r.y0 + 1, S.reg_h);
+  return r;
+}
+
+template <int SRC>
+__device__ __forceinline__ void stage_tile(const LaunchK& K, int u0, int v0, float2* lds, Region* regs,
+                                           int tid, int nthreads) {
+  for (int s = 0; s < K.n_sensors; ++s) {
+    const SensorK& S = K.s[s];
+    const Region r = tile_region(K, S, u0, v0);
+    regs[s] = r;
+    float2* dst = lds + S.lds_off;
+    const int total = r.w * r.h;
+    for (int e = tid; e < total; e += nthreads) {
+      const int row = e / r.w;
+      const int col = e - row * r.w;
+      dst[e] = load_sample<SRC>(S, r.x0 + col, r.y0 + row);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-pixel fit of one tile.  All loop bounds are uniform across the wave.
+// ---------------------------------------------------------------------------
+
+// Below this equilibrated pivot the variance of a fit is recomputed from the
+// samples as sum_k (g . phi_k)^2 K_k w_k (all terms positive) instead of the
+// moment form g^T B g, whose FP32 rounding grows like u / rho^2 (and faster
+// where the support is lopsided).
+constexpr float kRhoVarPass = 1e-1f;
+
+// Calls fn(dx, dy, f, iv) for every CFA sample of channel c inside the box of
+// radius index m around (Xj, Yj), over all sensors (scaled offsets).
+template <class Fn>
+__device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds, const Region* regs,
+                                             double Xj, double Yj, int c, int cls, int m, Fn&& fn) {
+  const ScaleK& SC = K.sc[m];
+  const double rad = SC.radius[cls];
+  const float cs = SC.coord_scale[cls];
+  for (int s = 0; s < K.n_sensors; ++s) {
+    const SensorK& S = K.s[s];
+    const Region R = regs[s];
+    // lane position on the sensor and the box half-widths of this radius
+    const double px = S.inv[0] * Xj + S.inv[1] * Yj + S.inv[2];
+    const double py = S.inv[3] * Xj + S.inv[4] * Yj + S.inv[5];
+    const double wx = rad * S.rownorm[0];
+    const double wy = rad * S.rownorm[1];
+    const int nx = S.nbox[cls][m][0];
+    const int ny = S.nbox[cls][m][1];
+    // step between sub-lattice points (+2 px in x or y), scaled
+    const float sax = (float)(2.0 * S.fwd[0]) * cs, say = (float)(2.0 * S.fwd[3]) * cs;
+    const float sbx = (float)(2.0 * S.fwd[1]) * cs, sby = (float)(2.0 * S.fwd[4]) * cs;
+    const float2* plane = lds + S.lds_off;
+    const int nsub = S.sub_n[c];
+    for (int q = 0; q < nsub; ++q) {
+      const int ox = S.sub_ox[c][q], oy = S.sub_oy[c][q];
+      // first sub-lattice point with |x - px| < wx (same for y)
+      const int xb = ox + 2 * (int)ceil((px - wx - ox) * 0.5);
+      const int yb = oy + 2 * (int)ceil((py - wy - oy) * 0.5);
+      // offset of that point from the output position, formed in FP64
+      const double Xb = S.fwd[0] * xb + S.fwd[1] * yb + S.fwd[2];
+      const double Yb = S.fwd[3] * xb + S.fwd[4] * yb + S.fwd[5];
+      const float c0x = (float)((Xb - Xj) * cs);
+      const float c0y = (float)((Yb - Yj) * cs);
+      const float2* p0 = plane + (yb - R.y0) * R.w + (xb - R.x0);
+      for (int jj = 0; jj < ny; ++jj) {
+        const float rx = __builtin_fmaf((float)jj, sbx, c0x);
+        const float ry = __builtin_fmaf((float)jj, sby, c0y);
+        const float2* prow = p0 + 2 * jj * R.w;
+        for (int ii = 0; ii < nx; ++ii) {
+          const float dx = __builtin_fmaf((float)ii, sax, rx);
+          const float dy = __builtin_fmaf((float)ii, say, ry);
+          const float2 sm = prow[2 * ii];
+          fn(dx, dy, sm.x, sm.y);
+        }
+      }
+    }
+  }
+}
+
+template <int ORDER, bool ICI>
+__device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, const Region* regs,
+                                          int u, int v, bool active) {
+  const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
+  const double Yj = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
+  float rgb[3], sdv[3];
+  uint8_t code[3];
+
+  for (int c = 0; c < 3; ++c) {
+    const int cls = (c == 1) ? 1 : 0;
+    IciState st[ORDER + 1];
+#pragma unroll
+    for (int o = 0; o <= ORDER; ++o) ici_init(st[o]);
+
+    for (int m = 0; m < K.n_scales; ++m) {
+      const float kexp = K.sc[m].k_exp[cls];
+      const float eedge = K.sc[m].e_edge[cls];
+      Acc<ORDER, ICI> a;
+      acc_zero(a);
+      walk_support(K, lds, regs, Xj, Yj, c, cls, m, [&](float dx, float dy, float f, float iv) {
+        acc_sample<ORDER, ICI>(a, dx, dy, f, iv, kexp, eedge);
+      });
+
+      Fits<float, ORDER> fr;
+      solve_fits<float, ORDER, ICI>(a.m, a.b, a.B, a.n, K.tau_inv, fr);
+      if constexpr (ORDER == 2) {
+        // FP64 re-solve of ill-conditioned order-2 systems from the FP32 moments
+        if (K.use_fp64 && a.n >= 6 && fr.rho[2] < K.tau_fp64 && fr.rho[0] > 0.f) {
+          double md[n_mom<ORDER>()], bd[n_basis<ORDER>()], Bd[ICI ? n_mom<ORDER>() : 1];
+#pragma unroll
+          for (int k = 0; k < n_mom<ORDER>(); ++k) md[k] = a.m[k];
+#pragma unroll
+          for (int k = 0; k < n_basis<ORDER>(); ++k) bd[k] = a.b[k];
+#pragma unroll
+          for (int k = 0; k < (ICI ? n_mom<ORDER>() : 1); ++k) Bd[k] = a.B[k];
+          Fits<double, ORDER> fd;
+          solve_fits<double, ORDER, ICI>(md, bd, Bd, a.n, (double)K.tau_inv, fd);
+#pragma unroll
+          for (int o = 0; o <= ORDER; ++o) {
+            fr.y[o] = (float)fd.y[o];
+            fr.v[o] = (float)fd.v[o];
+            fr.ok[o] = fd.ok[o];
+            fr.rho[o] = (float)fd.rho[o];
+#pragma unroll
+            for (int i = 0; i < n_basis<ORDER>(); ++i) fr.g[o][i] = (float)fd.g[o][i];
+          }
+        }
+      }
+      if constexpr (ICI && ORDER >= 1) {
+        // Variance of ill-conditioned fits from the samples (positive terms).
+        bool need = false;
+#pragma unroll
+        for (int o = 1; o <= ORDER; ++o) need = need || (fr.ok[o] && fr.rho[o] < kRhoVarPass);
+        if (need) {
+          float vs[ORDER + 1];
+#pragma unroll
+          for (int o = 0; o <= ORDER; ++o) vs[o] = 0.f;
+          walk_support(K, lds, regs, Xj, Yj, c, cls, m, [&](float dx, float dy, float f, float iv) {
+            (void)f;
+            const float x2 = dx * dx, y2 = dy * dy;
+            const float kw = fmaxf(__builtin_amdgcn_exp2f((x2 + y2) * kexp) - eedge, 0.f);
+            const float w2 = kw * kw * iv;
+            float phi[6] = {1.f, dx, dy, x2, dx * dy, y2};
+#pragma unroll
+            for (int o = 1; o <= ORDER; ++o) {
+              constexpr int nb_tab[3] = {1, 3, 6};
+              float t = fr.g[o][0];
+#pragma unroll
+              for (int i = 1; i < nb_tab[o]; ++i) t = __builtin_fmaf(fr.g[o][i], phi[i], t);
+              vs[o] = __builtin_fmaf(t * t, w2, vs[o]);
+            }
+          });
+#pragma unroll
+          for (int o = 1; o <= ORDER; ++o)
+            if (fr.rho[o] < kRhoVarPass) fr.v[o] = vs[o];
+        }
+      }
+#pragma unroll
+      for (int o = 0; o <= ORDER; ++o) ici_step(st[o], fr.ok[o], fr.y[o], fr.v[o], K.gamma, m);
+    }
+
+    float val = __builtin_nanf(""), sdc = __builtin_nanf("");
+    uint8_t cd = 0xFF;
+#pragma unroll
+    for (int o = ORDER; o >= 0; --o) {
+      if (cd == 0xFF && st[o].any) {
+        val = st[o].y;
+        sdc = st[o].sd;
+        cd = (uint8_t)((o << 4) | st[o].chosen);
+      }
+    }
+    rgb[c] = val;
+    sdv[c] = sdc;
+    code[c] = cd;
+  }
+
+  if (active) {
+    float* orow = reinterpret_cast<float*>(reinterpret_cast<char*>(K.rgb) + (int64_t)v * K.rgb_pitch);
+    orow[3 * u + 0] = rgb[0];
+    orow[3 * u + 1] = rgb[1];
+    orow[3 * u + 2] = rgb[2];
+    if (K.map) {
+      uint8_t* mrow = K.map + (int64_t)v * K.map_pitch;
+      mrow[3 * u + 0] = code[0];
+      mrow[3 * u + 1] = code[1];
+      mrow[3 * u + 2] = code[2];
+    }
+    if (K.sd) {
+      float* srow = reinterpret_cast<float*>(reinterpret_cast<char*>(K.sd) + (int64_t)v * K.sd_pitch);
+      srow[3 * u + 0] = sdv[0];
+      srow[3 * u + 1] = sdv[1];
+      srow[3 * u + 2] = sdv[2];
+    }
+  }
+}
+
+template <int ORDER, bool ICI, int SRC>
+__device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2* lds, Region* regs) {
+  const int tx = tile % K.tiles_x;
+  const int ty = tile / K.tiles_x;
+  const int u0 = tx * K.tile_w, v0 = ty * K.tile_h;
+  const int tid = threadIdx.x;
+  const int nthreads = K.tile_w * K.tile_h;
+  stage_tile<SRC>(K, u0, v0, lds, regs, tid, nthreads);
+  __syncthreads();
+  const int u = u0 + tid % K.tile_w;
+  const int v = v0 + tid / K.tile_w;
+  const bool active = (u < K.out_w) && (v < K.out_h);
+  fit_pixel<ORDER, ICI>(K, lds, regs, active ? u : u0, active ? v : v0, active);
+}
+
+template <int ORDER, bool ICI, int SRC>
+__global__ void __launch_bounds__(256) fit_kernel(const LaunchK K) {
+  extern __shared__ float2 lds[];
+  __shared__ Region regs[kMaxSensors];
+  process_tile<ORDER, ICI, SRC>(K, blockIdx.x, lds, regs);
+}
+
+// Persistent form: workgroups take tiles from a device counter until the
+// queue is exhausted; every workgroup reaches the exit test each round.  The
+// frame's order and single/multi-radius class select the fit code per tile
+// (a workgroup-uniform branch); all frames of one launch share SRC.
+template <int SRC>
+__global__ void __launch_bounds__(256) fit_batch_kernel(const BatchHeader* __restrict__ hdr,
+                                                       const LaunchK* __restrict__ frames,
+                                                       const int64_t* __restrict__ first_tile,
+                                                       int* __restrict__ queue) {
+  extern __shared__ float2 lds[];
+  __shared__ Region regs[kMaxSensors];
+  __shared__ int next_tile;
+  const int n_frames = hdr->n_frames;
+  const int64_t total_tiles = hdr->total_tiles;
+  for (;;) {
+    if (threadIdx.x == 0) next_tile = atomicAdd(queue, 1);
+    __syncthreads();
+    const int t = next_tile;
+    __syncthreads();
+    if ((int64_t)t >= total_tiles) break;
+    // frame owning global tile t (binary search over first-tile offsets)
+    int lo = 0, hi = n_frames - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (first_tile[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int f = __builtin_amdgcn_readfirstlane(lo);
+    const LaunchK& K = frames[f];
+    const int local = (int)(t - first_tile[f]);
+    switch (K.order * 2 + (K.need_var ? 1 : 0)) {
+      case 0: process_tile<0, false, SRC>(K, local, lds, regs); break;
+      case 1: process_tile<0, true, SRC>(K, local, lds, regs); break;
+      case 2: process_tile<1, false, SRC>(K, local, lds, regs); break;
+      case 3: process_tile<1, true, SRC>(K, local, lds, regs); break;
+      case 4: process_tile<2, false, SRC>(K, local, lds, regs); break;
+      default: process_tile<2, true, SRC>(K, local, lds, regs); break;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pre-pass: raw -> (radiance, inverse variance) FP32 plane, or raw ->
+// FP16 normalised radiance (y - b) 2^-bits, round-to-nearest-even, +Inf masked.
+// ---------------------------------------------------------------------------
+template <bool RAW_F32, bool TO_F16>
+__global__ void __launch_bounds__(256) prepass_kernel(const SensorK S, const void* raw, int64_t raw_pitch,
+                                                      void* plane, int64_t plane_pitch, float norm_encode) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= S.width || y >= S.height) return;
+  const char* rrow = static_cast<const char*>(raw) + (int64_t)y * raw_pitch;
+  const float dn = RAW_F32 ? reinterpret_cast<const float*>(rrow)[x]
+                           : (float)reinterpret_cast<const uint16_t*>(rrow)[x];
+  char* prow = static_cast<char*>(plane) + (int64_t)y * plane_pitch;
+  if constexpr (TO_F16) {
+    const __half h = (dn < S.sat) ? __float2half_rn((dn - S.black) * norm_encode)
+                                  : __ushort_as_half((unsigned short)0x7C00u);
+    reinterpret_cast<__half*>(prow)[x] = h;
+  } else {
+    reinterpret_cast<float2*>(prow)[x] = decode_dn(S, dn);
+  }
+}
+
+}  // namespace lpa
+
+using namespace lpa;
+
+namespace {
+constexpr int kMaxLdsBytes = 64 * 1024;
+
+template <int ORDER, bool ICI>
+int launch_fit_src(const LaunchK& K, hipStream_t st) {
+  const dim3 grid(K.tiles_x * K.tiles_y), block(K.tile_w * K.tile_h);
+  const size_t lds = (size_t)K.lds_floats2 * sizeof(float2);
+  switch (K.src_kind) {
+    case SRC_RAW_U16: fit_kernel<ORDER, ICI, SRC_RAW_U16><<<grid, block, lds, st>>>(K); break;
+    case SRC_RAW_F32: fit_kernel<ORDER, ICI, SRC_RAW_F32><<<grid, block, lds, st>>>(K); break;
+    case SRC_PLANE_F32: fit_kernel<ORDER, ICI, SRC_PLANE_F32><<<grid, block, lds, st>>>(K); break;
+    case SRC_PLANE_F16: fit_kernel<ORDER, ICI, SRC_PLANE_F16><<<grid, block, lds, st>>>(K); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace
+
+extern "C" int lpa_k_fit_max_lds_bytes(void) { return kMaxLdsBytes; }
+
+extern "C" int lpa_k_fit(const LaunchK* k, void* stream) {
+  const LaunchK& K = *k;
+  if (K.tile_w * K.tile_h > 256 || (size_t)K.lds_floats2 * sizeof(float2) > (size_t)kMaxLdsBytes) return -1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (K.order * 2 + (K.need_var ? 1 : 0)) {
+    case 0: return launch_fit_src<0, false>(K, st);
+    case 1: return launch_fit_src<0, true>(K, st);
+    case 2: return launch_fit_src<1, false>(K, st);
+    case 3: return launch_fit_src<1, true>(K, st);
+    case 4: return launch_fit_src<2, false>(K, st);
+    case 5: return launch_fit_src<2, true>(K, st);
+    default: return -1;
+  }
+}
+
+extern "C" int lpa_k_prepass(const SensorK* s, int raw_is_f32, const void* raw, int64_t raw_pitch,
+                             void* plane, int64_t plane_pitch, int to_f16, float norm_encode,
+                             void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid((s->width + 63) / 64, (s->height + 3) / 4), block(256);
+  if (raw_is_f32) {
+    if (to_f16) prepass_kernel<true, true><<<grid, block, 0, st>>>(*s, raw, raw_pitch, plane, plane_pitch, norm_encode);
+    else prepass_kernel<true, false><<<grid, block, 0, st>>>(*s, raw, raw_pitch, plane, plane_pitch, norm_encode);
+  } else {
+    if (to_f16) prepass_kernel<false, true><<<grid, block, 0, st>>>(*s, raw, raw_pitch, plane, plane_pitch, norm_encode);
+    else prepass_kernel<false, false><<<grid, block, 0, st>>>(*s, raw, raw_pitch, plane, plane_pitch, norm_encode);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+extern "C" int lpa_k_fit_batch(const BatchHeader* d_hdr, const LaunchK* d_frames,
+                               const int64_t* d_first_tile, int32_t* d_queue, int32_t src_kind,
+                               int32_t block, int32_t lds_floats2, int32_t grid, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t lds = (size_t)lds_floats2 * sizeof(float2);
+  if (block > 256 || lds > (size_t)kMaxLdsBytes) return -1;
+  switch (src_kind) {
+    case SRC_RAW_U16: fit_batch_kernel<SRC_RAW_U16><<<grid, block, lds, st>>>(d_hdr, d_frames, d_first_tile, d_queue); break;
+    case SRC_RAW_F32: fit_batch_kernel<SRC_RAW_F32><<<grid, block, lds, st>>>(d_hdr, d_frames, d_first_tile, d_queue); break;
+    case SRC_PLANE_F32: fit_batch_kernel<SRC_PLANE_F32><<<grid, block, lds, st>>>(d_hdr, d_frames, d_first_tile, d_queue); break;
+    case SRC_PLANE_F16: fit_batch_kernel<SRC_PLANE_F16><<<grid, block, lds, st>>>(d_hdr, d_frames, d_first_tile, d_queue); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+namespace {
+__global__ void zero_i32_kernel(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+}  // namespace
+
+// Clears n ints with a kernel (not a memset node, so it is safe inside graphs).
+extern "C" int lpa_k_zero_i32(int32_t* p, int32_t n, void* stream) {
+  zero_i32_kernel<<<(n + 255) / 256, 256, 0, static_cast<hipStream_t>(stream)>>>(p, n);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}

@@ -1,0 +1,291 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every comparison uses seeded synthetic inputs from ``synth`` and the metric and
+tolerances of ``parity_utils`` (derived there from the arithmetic).  Sizes:
+full frames where the oracle finishes in seconds (several tiles and a ragged
+tail), sampled pixels at the full 4 x 2048^2 size.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import configs, rig as R
+from synth.scene import EdgeScene, PolynomialScene, StepScene
+from parity_utils import compare, firm_mask, floor_of, fp16_round_dn
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_mod):
+    from paper_1308_4908_amd import Context
+
+    c = Context(0)
+    yield c
+    torch_mod.cuda.synchronize()
+    c.close()
+
+
+def run_gpu(torch, ctx, sensors, raws, params, plain=False):
+    from paper_1308_4908_amd import Rig
+
+    rig = Rig(ctx, sensors)
+    dev = [torch.from_numpy(np.ascontiguousarray(r)).cuda() for r in raws]
+    out = torch.full((params["out_h"], params["out_w"], 3), -12345.0, dtype=torch.float32, device="cuda")
+    smap = torch.full((params["out_h"], params["out_w"], 3), 0xEE, dtype=torch.uint8, device="cuda")
+    sd = torch.full((params["out_h"], params["out_w"], 3), -1.0, dtype=torch.float32, device="cuda")
+    rig.reconstruct(dev, params, out, smap, plain=plain, sd_map=sd)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy(), smap.cpu().numpy()
+    LAST_SD[0] = sd.cpu().numpy()
+    rig.close()
+    return res
+
+
+# standard deviations written by the last run_gpu call (checked by compare)
+LAST_SD = [None]
+
+
+def pixels_of(u, v):
+    return np.stack([np.asarray(u).ravel(), np.asarray(v).ravel()], 1).astype(np.int32)
+
+
+def sample_pixels(w, h, n, seed):
+    rng = np.random.default_rng(seed)
+    u = rng.integers(0, w, n)
+    v = rng.integers(0, h, n)
+    # borders, corners and the last (ragged) tile
+    eu = np.concatenate([np.arange(w)[:: max(1, w // 64)], [0, w - 1, 0, w - 1], np.arange(max(0, w - 20), w)])
+    ev = np.concatenate([np.zeros_like(np.arange(w)[:: max(1, w // 64)]), [0, 0, h - 1, h - 1],
+                         np.full(min(20, w), h - 1)])
+    return pixels_of(np.concatenate([u, eu]), np.concatenate([v, ev]))
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage", ["fused", "fp32"])
+def test_small_full_frame(torch_mod, ctx, storage):
+    """3 x 256^2, order 1, radius 2: every output pixel against the oracle."""
+    sensors, scene, params = configs.small()
+    raws = configs.capture_all(scene, sensors, 1000)
+    params = dict(params, storage=storage)
+    _say(f"[gpu] small full frame storage={storage}")
+    rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, params)
+    orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
+    st = compare(rgb, smap, orc, sensors, params["order"], gpu_sd=LAST_SD[0])
+    _say(f"  stats {st}")
+    assert st["firm_frac"] > 0.99
+
+
+def test_plain_equals_fused(torch_mod, ctx):
+    """The plain form (pre-pass planes, fixed tile) computes the same values."""
+    sensors, scene, params = configs.small(seed=1001)
+    raws = configs.capture_all(scene, sensors, 1001)
+    _say("[gpu] plain vs fused")
+    a, ma = run_gpu(torch_mod, ctx, sensors, raws, params)
+    b, mb = run_gpu(torch_mod, ctx, sensors, raws, params, plain=True)
+    assert np.array_equal(a, b, equal_nan=True)
+    assert np.array_equal(ma, mb)
+
+
+@pytest.mark.parametrize("order,radii", [(0, [2.0]), (0, [1.5, 3.0]), (1, [1.0, 2.0, 3.0, 4.0]),
+                                         (2, [3.0]), (2, [1.0, 2.0, 3.0, 4.0])])
+def test_orders_and_scales(torch_mod, ctx, order, radii):
+    """4 sensors like the full workload, 96^2 output (6 x 6 tiles, no ragged edge
+    is hidden: 96 = 6 * 16) plus a 37 x 23 ragged frame."""
+    sensors = configs.full_rig(seed=2100, size=96)
+    scene = EdgeScene(96, 96, 2100, n_lines=12)
+    raws = configs.capture_all(scene, sensors, 2100)
+    for (w, h) in ((96, 96), (37, 23)):
+        params = configs.lpa_params(w, h, order, radii, out_affine=[1, 0, 20.5, 0, 1, 30.25] if w == 37 else None)
+        _say(f"[gpu] order={order} radii={radii} out={w}x{h}")
+        rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, params)
+        orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
+        st = compare(rgb, smap, orc, sensors, order, gpu_sd=LAST_SD[0])
+        _say(f"  stats {st}")
+        assert st["firm_frac"] > (0.7 if order == 2 else 0.9)
+        assert st["agree_frac"] > 0.99
+
+
+def test_full_size_sampled(torch_mod, ctx):
+    """4 x 2048^2, order 2, ICI {1,2,3,4}: sampled pixels (random + borders +
+    ragged corner) against the oracle computed pixel by pixel, in the launch
+    configuration the benchmark times."""
+    sensors, scene, params = configs.full()
+    _say("[gpu] generating 4 x 2048^2 frame")
+    raws = configs.capture_all(scene, sensors, 2000)
+    _say("[gpu] full-size run")
+    rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, params)
+    pix = sample_pixels(2048, 2048, 1500, 77)
+    orc = oracle.reconstruct(sensors, raws, params, pixels=pix, want_fits=True)
+    g = rgb[pix[:, 1], pix[:, 0]]
+    m = smap[pix[:, 1], pix[:, 0]]
+    st = compare(g, m, orc, sensors, 2, gpu_sd=LAST_SD[0][pix[:, 1], pix[:, 0]])
+    _say(f"  stats {st}")
+    assert st["firm_frac"] > 0.7
+    assert st["agree_frac"] > 0.99
+    # every pixel was written and carries a valid code
+    assert not np.any(rgb == -12345.0)
+    assert not np.any(smap == 0xEE)
+
+
+def test_fp16_storage(torch_mod, ctx):
+    """FP16 normalised-radiance storage: against the oracle fed the same
+    FP16-rounded samples (FP32 tolerance) and against the exact oracle (2e-3)."""
+    sensors = configs.full_rig(seed=2200, size=128)
+    scene = EdgeScene(128, 128, 2200, n_lines=10)
+    raws = configs.capture_all(scene, sensors, 2200)
+    params = configs.lpa_params(128, 128, 2, [1.0, 2.0, 3.0, 4.0], storage="fp16")
+    _say("[gpu] fp16 storage 4 x 128^2 order 2 ICI")
+    rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, params)
+    conv = [fp16_round_dn(r, s) for r, s in zip(raws, sensors)]
+    orc16 = oracle.reconstruct([c[1] for c in conv], [c[0] for c in conv], params, want_fits=True)
+    st = compare(rgb, smap, orc16, sensors, 2)
+    _say(f"  vs fp16-fed oracle {st}")
+    orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
+    both = firm_mask(orc, 2, sensors) & firm_mask(orc16, 2, sensors) & (orc["scale_map"] == orc16["scale_map"])
+    y = rgb.reshape(-1, 3)[both]
+    ref = orc["rgb"][both]
+    ok = ~np.isnan(ref)
+    e = np.abs(y[ok] - ref[ok]) / np.maximum(np.abs(ref[ok]), floor_of(sensors))
+    _say(f"  vs exact oracle: max {e.max():.3e} p50 {np.median(e):.3e}")
+    assert e.max() <= 2e-3
+
+
+def test_resampled_output(torch_mod, ctx):
+    """Arbitrary output mapping: the 3 x 256^2 rig reconstructed on a 16x finer
+    grid (4096^2) with FP16 storage; sampled pixels against the oracle fed the
+    FP16-rounded samples."""
+    sensors, scene, params = configs.resampled()
+    raws = configs.capture_all(scene, sensors, 3000)
+    _say("[gpu] resampled 4096^2 output")
+    rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, params)
+    pix = sample_pixels(4096, 4096, 1500, 78)
+    conv = [fp16_round_dn(r, s) for r, s in zip(raws, sensors)]
+    orc = oracle.reconstruct([c[1] for c in conv], [c[0] for c in conv], params, pixels=pix, want_fits=True)
+    st = compare(rgb[pix[:, 1], pix[:, 0]], smap[pix[:, 1], pix[:, 0]], orc, sensors, 1)
+    _say(f"  stats {st}")
+
+
+def test_noise_free_polynomial_exact(torch_mod, ctx):
+    """Noise-free quadratic radiance (float DN input): the order-2 estimate is
+    the field value, and ICI keeps the largest valid radius (all estimates
+    coincide) -- scale maps must equal the oracle's bit for bit."""
+    rng = np.random.default_rng(5)
+    coeffs = np.zeros((3, 6))
+    coeffs[:, 0] = rng.uniform(500, 900, 3)
+    coeffs[:, 1:3] = rng.uniform(-4, 4, (3, 2))
+    coeffs[:, 3:6] = rng.uniform(-0.02, 0.02, (3, 3))
+    scene = PolynomialScene(coeffs)
+    sensors = configs.full_rig(seed=2300, size=64)
+    raws = [R.capture_noise_free(scene, s) for s in sensors]
+    params = configs.lpa_params(40, 40, 2, [1.0, 2.0, 3.0, 4.0], out_affine=[1, 0, 12, 0, 1, 12])
+    _say("[gpu] noise-free polynomial")
+    rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, params)
+    orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
+    u, v = np.meshgrid(np.arange(40.0) + 12, np.arange(40.0) + 12)
+    truth = np.stack([scene.radiance(u, v, c) for c in range(3)], -1)
+    np.testing.assert_allclose(rgb, truth, rtol=2e-5)
+    firm = firm_mask(orc, 2, sensors)
+    assert firm.mean() > 0.7
+    assert np.array_equal(smap.reshape(-1, 3), orc["scale_map"])
+
+
+def test_noise_free_step_edge_ici_exact(torch_mod, ctx):
+    """Axis-aligned step edge, aligned and integer-translated sensors, noise-free:
+    a finite set of support geometries.  The oracle's margins are checked to be
+    firm, and the GPU's ICI scale map must then match it everywhere."""
+    scene = StepScene(20.0, 300.0, 3000.0)
+    sensors = [R.make_sensor(48, 48, [1, 0, t[0], 0, 1, t[1]], e)
+               for t, e in (((0, 0), 1.0), ((1, 0), 0.25), ((0, 1), 1 / 16), ((1, 1), 1 / 64))]
+    raws = [R.capture_noise_free(scene, s) for s in sensors]
+    params = configs.lpa_params(32, 32, 2, [1.0, 2.0, 3.0, 4.0], out_affine=[1, 0, 6, 0, 1, 6])
+    _say("[gpu] noise-free step edge ICI")
+    rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, params)
+    orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
+    firm = firm_mask(orc, 2, sensors)
+    assert firm.all(), f"{np.count_nonzero(~firm)} oracle decisions near a tie"
+    assert np.array_equal(smap.reshape(-1, 3), orc["scale_map"])
+    compare(rgb, smap, orc, sensors, 2)
+
+
+def test_edge_cases(torch_mod, ctx):
+    """1 x 1 output; an output grid entirely off the sensors (no samples: NaN and
+    0xFF); a fully saturated sensor set (NaN); a single sensor rig."""
+    sensors, scene, params = configs.small(size=64)
+    raws = configs.capture_all(scene, sensors, 1002)
+    _say("[gpu] edge cases")
+    one = dict(params, out_w=1, out_h=1, out_affine=[1, 0, 31.3, 0, 1, 17.8])
+    rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, one)
+    orc = oracle.reconstruct(sensors, raws, one, want_fits=True)
+    compare(rgb, smap, orc, sensors, 1)
+    off = dict(params, out_w=20, out_h=20, out_affine=[1, 0, 500.0, 0, 1, 500.0])
+    rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, off)
+    assert np.all(np.isnan(rgb)) and np.all(smap == 0xFF)
+    sat = [np.full_like(r, 4095) for r in raws]
+    rgb, smap = run_gpu(torch_mod, ctx, sensors, sat, dict(params, out_w=16, out_h=16))
+    assert np.all(np.isnan(rgb)) and np.all(smap == 0xFF)
+    single = [sensors[1]]
+    p1 = dict(params, out_w=48, out_h=40)
+    rgb, smap = run_gpu(torch_mod, ctx, single, [raws[1]], p1)
+    orc = oracle.reconstruct(single, [raws[1]], p1, want_fits=True)
+    compare(rgb, smap, orc, single, 1)
+
+
+def test_sensor_order_invariance(torch_mod, ctx):
+    """Permuting the sensors (frames and descriptors together) changes only the
+    summation order: both runs pass parity and make the same firm decisions."""
+    sensors = configs.full_rig(seed=2400, size=64)
+    scene = EdgeScene(64, 64, 2400, n_lines=6)
+    raws = configs.capture_all(scene, sensors, 2400)
+    params = configs.lpa_params(64, 64, 2, [1.0, 2.0, 3.0, 4.0])
+    _say("[gpu] sensor order invariance")
+    a, ma = run_gpu(torch_mod, ctx, sensors, raws, params)
+    perm = [3, 1, 0, 2]
+    b, mb = run_gpu(torch_mod, ctx, [sensors[i] for i in perm], [raws[i] for i in perm], params)
+    orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
+    compare(a, ma, orc, sensors, 2)
+    compare(b, mb, orc, sensors, 2)
+    firm = firm_mask(orc, 2, sensors).reshape(64, 64, 3)
+    assert np.array_equal(ma[firm], mb[firm])
+
+
+def test_invalid_arguments_leave_output_untouched(torch_mod, ctx):
+    from paper_1308_4908_amd import LpaError, Rig, lpa
+
+    sensors, scene, params = configs.small(size=32)
+    raws = configs.capture_all(scene, sensors, 1003)
+    rig = Rig(ctx, sensors)
+    dev = [torch_mod.from_numpy(r).cuda() for r in raws]
+    out = torch_mod.full((32, 32, 3), 7.0, device="cuda")
+    bad = [dict(params, order=3), dict(params, radii=[2.0, 1.0]), dict(params, gamma=0.0, radii=[1.0, 2.0]),
+           dict(params, out_w=0), dict(params, storage=9), dict(params, radii=[0.0])]
+    for p in bad:
+        with pytest.raises(LpaError) as ei:
+            rig.reconstruct(dev, p, out)
+        assert ei.value.status == lpa.ERR_INVALID_ARG
+    with pytest.raises(LpaError):
+        rig.reconstruct(dev[:2], params, out)  # wrong sensor count
+    torch_mod.cuda.synchronize()
+    assert torch_mod.all(out == 7.0)
+    with pytest.raises(LpaError):
+        Rig(ctx, [dict(sensors[0], gain=0.0)])
+    with pytest.raises(LpaError):
+        Rig(ctx, [dict(sensors[0], affine=[1, 2, 0, 2, 4, 0])])
+    rig.close()

@@ -425,10 +425,12 @@ def test_ici_worked_examples():
     with open(os.path.join(GOLDEN, "ici_worked_examples.json")) as fh:
         cases = json.load(fh)["cases"]
     for c in cases:
-        k, mu = oracle.ici_select(c["yhat"], c["var"], c["valid"], c["gamma"])
+        k, mu, gap = oracle.ici_select(c["yhat"], c["var"], c["valid"], c["gamma"])
         assert k == c["chosen"], c["name"]
         want = math.inf if c["margin"] == "inf" else c["margin"]
         assert mu == pytest.approx(want), c["name"]
+        want = math.inf if c["gap"] == "inf" else c["gap"]
+        assert gap == pytest.approx(want), c["name"]
 
 
 @pytest.mark.parametrize("order", [1, 2])
