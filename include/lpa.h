@@ -150,7 +150,8 @@ typedef struct lpa_rig lpa_rig;
  * library's own buffers (0 = 90% of free memory).  The context owns its
  * streams, scratch planes, autotune cache and serving scheduler. */
 lpa_status lpa_create_ctx(int device, size_t hbm_budget_bytes, lpa_ctx** out);
-/* Wait for all work of the context, stop its scheduler, free everything. */
+/* Wait for all work of the context, stop its scheduler, free everything,
+ * including rigs not yet destroyed (their handles become invalid). */
 lpa_status lpa_destroy_ctx(lpa_ctx* ctx);
 
 /* Create a rig: the descriptor is validated and copied (caller may free it);
@@ -159,6 +160,7 @@ lpa_status lpa_destroy_ctx(lpa_ctx* ctx);
  * gain, exposure, read_sigma > 0, invertible affine, finite values,
  * saturation > black_level, 1 <= bit_depth <= 16. */
 lpa_status lpa_create_rig(lpa_ctx* ctx, const lpa_rig_desc* desc, lpa_rig** out);
+/* Waits for the context's queued and running work, then frees the rig. */
 lpa_status lpa_destroy_rig(lpa_rig* rig);
 
 /* Reconstruct one frame, stream-ordered on `hip_stream` (a hipStream_t; NULL

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 namespace lpa {
 
@@ -24,6 +25,7 @@ lpa_status set_error(lpa_status st, const char* fmt, ...) {
 
 lpa_status device_error(lpa_ctx* ctx, hipError_t e, const char* what) {
   if (ctx) ctx->failed.store(true);
+  (void)hipGetLastError();  // leave no error state behind for the caller's own HIP calls
   return set_error(LPA_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
@@ -276,36 +278,39 @@ lpa_status check_ctx(lpa_ctx* ctx) {
 }
 
 // Scratch planes for the pre-pass forms, stream-ordered (hipMallocAsync).
-lpa_status alloc_async(lpa_ctx* ctx, size_t bytes, hipStream_t st, void** p) {
-  size_t used = ctx->used.fetch_add(bytes) + bytes;
-  if (used > ctx->budget) {
-    ctx->used.fetch_sub(bytes);
-    return set_error(LPA_ERR_OOM, "HBM budget of %zu bytes exceeded", ctx->budget);
+lpa_status alloc_async(lpa_ctx* ctx, size_t bytes, hipStream_t st, void** p, bool charge) {
+  if (charge) {
+    size_t used = ctx->used.fetch_add(bytes) + bytes;
+    if (used > ctx->budget) {
+      ctx->used.fetch_sub(bytes);
+      return set_error(LPA_ERR_OOM, "HBM budget of %zu bytes exceeded", ctx->budget);
+    }
   }
   hipError_t e = hipMallocAsync(p, bytes, st);
   if (e != hipSuccess) {
-    ctx->used.fetch_sub(bytes);
+    if (charge) ctx->used.fetch_sub(bytes);
+    *p = nullptr;
     (void)hipGetLastError();
     return set_error(LPA_ERR_OOM, "hipMallocAsync(%zu): %s", bytes, hipGetErrorString(e));
   }
   return LPA_OK;
 }
 
-void free_async(lpa_ctx* ctx, void* p, size_t bytes, hipStream_t st) {
+void free_async(lpa_ctx* ctx, void* p, size_t bytes, hipStream_t st, bool charge) {
   if (!p) return;
   (void)hipFreeAsync(p, st);
-  ctx->used.fetch_sub(bytes);
+  if (charge) ctx->used.fetch_sub(bytes);
 }
 
 // Pre-pass every sensor into planes; fills srcs/pitches and the allocations.
 lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_t st, void** planes,
-                       size_t* plane_bytes, const void** srcs, int64_t* pitches) {
+                       size_t* plane_bytes, const void** srcs, int64_t* pitches, bool charge) {
   lpa_ctx* ctx = rig->ctx;
   for (int s = 0; s < rig->n; ++s) {
     const SensorK& S = rig->k[s];
     const int64_t pitch = ((int64_t)S.width * (to_f16 ? 2 : 8) + 255) / 256 * 256;
     plane_bytes[s] = (size_t)pitch * S.height;
-    lpa_status rs = alloc_async(ctx, plane_bytes[s], st, &planes[s]);
+    lpa_status rs = alloc_async(ctx, plane_bytes[s], st, &planes[s], charge);
     if (rs != LPA_OK) return rs;
     const float enc = std::ldexp(1.0f, -rig->desc[s].bit_depth);
     if (lpa_k_prepass(&S, f->dtype == LPA_DTYPE_F32, f->raw[s], f->row_pitch_bytes[s], planes[s], pitch,
@@ -409,9 +414,26 @@ lpa_status lpa_create_ctx(int device, size_t hbm_budget_bytes, lpa_ctx** out) {
   return LPA_OK;
 }
 
+static void rig_free(lpa_rig* rig) {
+  if (rig->d_k) {
+    (void)hipSetDevice(rig->ctx->device);
+    (void)hipFree(rig->d_k);
+  }
+  delete rig;
+}
+
 lpa_status lpa_destroy_ctx(lpa_ctx* ctx) {
   if (!ctx) return set_error(LPA_ERR_INVALID_ARG, "context is NULL");
   ctx_shutdown_runtime(ctx);
+  // rigs still alive are destroyed with their context
+  std::vector<lpa_rig*> rigs;
+  {
+    std::lock_guard<std::mutex> g(ctx->rigs_mu);
+    rigs.assign(ctx->rigs.begin(), ctx->rigs.end());
+    ctx->rigs.clear();
+  }
+  for (lpa_rig* r : rigs) rig_free(r);
+  (void)hipGetLastError();
   delete ctx;
   return LPA_OK;
 }
@@ -439,18 +461,27 @@ lpa_status lpa_create_rig(lpa_ctx* ctx, const lpa_rig_desc* desc, lpa_rig** out)
     delete rig;
     return device_error(ctx, e, "rig tables");
   }
+  {
+    std::lock_guard<std::mutex> g(ctx->rigs_mu);
+    ctx->rigs.insert(rig);
+  }
   *out = rig;
   return LPA_OK;
 }
 
 lpa_status lpa_destroy_rig(lpa_rig* rig) {
   if (!rig) return set_error(LPA_ERR_INVALID_ARG, "rig is NULL");
-  if (rig->d_k) {
-    (void)hipSetDevice(rig->ctx->device);
-    (void)hipDeviceSynchronize();
-    (void)hipFree(rig->d_k);
+  lpa_ctx* ctx = rig->ctx;
+  {
+    std::lock_guard<std::mutex> g(ctx->rigs_mu);
+    if (!ctx->rigs.erase(rig)) return set_error(LPA_ERR_INVALID_ARG, "rig is not live in its context");
   }
-  delete rig;
+  // frames of this rig may still be queued or running: wait for the context's work
+  if (ctx->sched) (void)lpa_drain(ctx);
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  rig_free(rig);
+  (void)hipGetLastError();
   return LPA_OK;
 }
 

@@ -32,7 +32,8 @@ static int src_kind_of(const lpa_params& p, const lpa_frame& f) {
 
 lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_frame* frames,
                           const lpa_params* params, const lpa_output* outs, hipStream_t stream,
-                          std::vector<LaunchK>* ks, int* src_kind, std::vector<PlaneAlloc>* planes) {
+                          std::vector<LaunchK>* ks, int* src_kind, std::vector<PlaneAlloc>* planes,
+                          bool charge) {
   ks->assign(n, LaunchK());
   int sk = -1;
   std::vector<Resolved> Rs(n);
@@ -71,7 +72,7 @@ lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_f
       size_t pb[LPA_MAX_SENSORS] = {0};
       const void* srcs[LPA_MAX_SENSORS];
       int64_t pitches[LPA_MAX_SENSORS];
-      lpa_status st = run_prepass(rigs[i], &frames[i], sk == SRC_PLANE_F16, stream, pl, pb, srcs, pitches);
+      lpa_status st = run_prepass(rigs[i], &frames[i], sk == SRC_PLANE_F16, stream, pl, pb, srcs, pitches, charge);
       for (int s = 0; s < rigs[i]->n; ++s)
         if (pl[s]) planes->push_back({pl[s], pb[s]});
       if (st != LPA_OK) return st;

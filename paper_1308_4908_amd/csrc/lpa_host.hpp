@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <deque>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -133,6 +134,9 @@ struct lpa_ctx {
   hipStream_t capture_stream = nullptr;
   // serving
   lpa::Scheduler* sched = nullptr;
+  // live rigs (destroyed with the context)
+  std::mutex rigs_mu;
+  std::set<lpa_rig*> rigs;
 };
 
 struct lpa_rig {
@@ -158,10 +162,12 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output*
 lpa_status build_launch_fit(const lpa_rig* rig, const Resolved& R, const lpa_output* out, int src_kind,
                             const void* const* srcs, const int64_t* pitches, int pref_w, int pref_h,
                             LaunchK* K);
-lpa_status alloc_async(lpa_ctx* ctx, size_t bytes, hipStream_t st, void** p);
-void free_async(lpa_ctx* ctx, void* p, size_t bytes, hipStream_t st);
+// Stream-ordered scratch; `charge` counts it against the context's HBM budget
+// (the serving scheduler charges a frame's whole footprint at admission).
+lpa_status alloc_async(lpa_ctx* ctx, size_t bytes, hipStream_t st, void** p, bool charge = true);
+void free_async(lpa_ctx* ctx, void* p, size_t bytes, hipStream_t st, bool charge = true);
 lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_t st, void** planes,
-                       size_t* plane_bytes, const void** srcs, int64_t* pitches);
+                       size_t* plane_bytes, const void** srcs, int64_t* pitches, bool charge = true);
 
 // Runtime pieces owned by a context (scheduler threads, batch tables).
 lpa_status ctx_init_runtime(lpa_ctx* ctx);
@@ -179,7 +185,8 @@ struct PlaneAlloc {
 };
 lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_frame* frames,
                           const lpa_params* params, const lpa_output* outs, hipStream_t stream,
-                          std::vector<LaunchK>* ks, int* src_kind, std::vector<PlaneAlloc>* planes);
+                          std::vector<LaunchK>* ks, int* src_kind, std::vector<PlaneAlloc>* planes,
+                          bool charge = true);
 lpa_status serve_init(lpa_ctx* ctx);
 void serve_shutdown(lpa_ctx* ctx);
 

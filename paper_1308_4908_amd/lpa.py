@@ -264,13 +264,19 @@ class Context:
     """A library context on one device (owns streams, tables, scheduler)."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        import weakref
+
         h = ctypes.c_void_p()
         check(lpa_create_ctx(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
         self.handle = h
         self.device = device
+        self._rigs = weakref.WeakSet()
 
     def close(self):
         if self.handle:
+            # the C context destroys its live rigs; mark their handles dead first
+            for r in list(self._rigs):
+                r.handle = None
             check(lpa_destroy_ctx(self.handle))
             self.handle = None
 
@@ -309,11 +315,12 @@ class Rig:
         self.handle = h
         self.ctx = ctx
         self.sensors = [dict(d) for d in sensors]
+        ctx._rigs.add(self)
 
     def close(self):
-        if self.handle:
+        if self.handle and self.ctx.handle:
             check(lpa_destroy_rig(self.handle))
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:

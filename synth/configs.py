@@ -24,7 +24,7 @@ from .scene import EdgeScene
 NOISE = dict(gain=0.5, read_sigma=3.0, black_level=64.0, saturation=4095.0, bit_depth=12, cfa="RGGB")
 
 
-def lpa_params(out_w, out_h, order, radii, out_affine=None, gamma=2.0, storage="fp32", **kw):
+def lpa_params(out_w, out_h, order, radii, out_affine=None, gamma=2.0, storage="fused", **kw):
     p = {
         "out_w": int(out_w), "out_h": int(out_h),
         "out_affine": list(out_affine) if out_affine is not None else _rig.identity_output(out_w, out_h),
@@ -51,7 +51,7 @@ def small(seed=1000, size=256):
     return sensors, scene, lpa_params(size, size, 1, [2.0])
 
 
-def full(seed=2000, size=2048, storage="fp32"):
+def full(seed=2000, size=2048, storage="fused"):
     """(sensors, scene, params) of the 4-sensor order-2 ICI workload."""
     sensors = full_rig(seed, size)
     scene = EdgeScene(size, size, seed)

@@ -1,0 +1,186 @@
+"""Batched and served forms: every frame's result equals the same frame
+reconstructed alone, bit for bit (the per-pixel computation does not depend on
+which frames share a launch), across graph replays and under budget pressure."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import configs
+from synth.scene import EdgeScene
+from parity_utils import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make_frames(n, seed0=4100):
+    """Small mixed frames: sizes, sensor counts, exposure sets and orders vary."""
+    rng = np.random.default_rng(seed0)
+    frames = []
+    for i in range(n):
+        w, h = [(96, 64), (64, 64), (80, 48)][i % 3]
+        ns = 2 + (i % 3)
+        exps = [1.0]
+        for _ in range(ns - 1):
+            exps.append(exps[-1] * 2.0 ** -int(rng.integers(2, 7)))
+        from synth import rig as R
+        sensors = R.random_rig(ns, w, h, exps, 2.0, 0.3, seed0 + i, **configs.NOISE)
+        scene = EdgeScene(w, h, seed0 + i, n_lines=6)
+        raws = configs.capture_all(scene, sensors, seed0 + i)
+        order = 1 + (i % 2)
+        params = configs.lpa_params(w, h, order, [1.0, 2.0, 3.0, 4.0])
+        frames.append((sensors, raws, params))
+    return frames
+
+
+def alone(torch, ctx, rig, raws_dev, params):
+    out = torch.empty((params["out_h"], params["out_w"], 3), dtype=torch.float32, device="cuda")
+    smap = torch.empty((params["out_h"], params["out_w"], 3), dtype=torch.uint8, device="cuda")
+    rig.reconstruct(raws_dev, params, out, smap)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), smap.cpu().numpy()
+
+
+@pytest.mark.parametrize("storage", ["fused", "fp16"])
+def test_batch_equals_alone_across_replays(torch_mod, storage):
+    torch = torch_mod
+    from paper_1308_4908_amd import Context, Rig
+
+    ctx = Context(0)
+    frames = make_frames(7)
+    rigs, devs, params, refs = [], [], [], []
+    for sensors, raws, p in frames:
+        p = dict(p, storage=storage)
+        rig = Rig(ctx, sensors)
+        dev = [torch.from_numpy(r).cuda() for r in raws]
+        rigs.append(rig)
+        devs.append(dev)
+        params.append(p)
+        refs.append(alone(torch, ctx, rig, dev, p))
+    # the first frame also against the oracle, to anchor the comparison
+    if storage == "fused":
+        s0, r0, p0 = frames[0]
+        st = compare(refs[0][0], refs[0][1], oracle.reconstruct(s0, r0, p0, want_fits=True), s0, p0["order"])
+        _say(f"[gpu] batch anchor frame vs oracle {st}")
+    for rep in range(3):
+        outs = [torch.full((p["out_h"], p["out_w"], 3), float(rep), device="cuda") for p in params]
+        maps = [torch.zeros((p["out_h"], p["out_w"], 3), dtype=torch.uint8, device="cuda") for p in params]
+        _say(f"[gpu] batch replay {rep} storage={storage}")
+        ctx.reconstruct_batch(rigs, devs, params, outs, maps)
+        torch.cuda.synchronize()
+        # eager work between replays
+        x = torch.randn(1 << 20, device="cuda").sum().item()
+        assert np.isfinite(x)
+        for i in range(len(frames)):
+            assert np.array_equal(outs[i].cpu().numpy(), refs[i][0], equal_nan=True), f"frame {i} replay {rep}"
+            assert np.array_equal(maps[i].cpu().numpy(), refs[i][1]), f"frame {i} replay {rep}"
+    for r in rigs:
+        r.close()
+    ctx.close()
+
+
+def _serve(torch, ctx, items, host_pinned=True):
+    """Submit items = [(rig, raws_np, params)] as fast as possible; returns outputs and results."""
+    outs, tickets, hosts = [], [], []
+    for rig, raws, p in items:
+        if host_pinned:
+            hs = [torch.from_numpy(r).pin_memory() for r in raws]
+        else:
+            hs = [np.ascontiguousarray(r) for r in raws]
+        hosts.append(hs)
+        out = torch.full((p["out_h"], p["out_w"], 3), -1.0, device="cuda")
+        smap = torch.zeros((p["out_h"], p["out_w"], 3), dtype=torch.uint8, device="cuda")
+        outs.append((out, smap))
+        t = None
+        while t is None:
+            t = rig.submit(hs, p, out, smap, arrival_ns=0, host=True)
+        tickets.append(t)
+    ctx.drain()
+    res = [ctx.poll(t) for t in tickets]
+    torch.cuda.synchronize()
+    return [(o.cpu().numpy(), m.cpu().numpy()) for o, m in outs], res
+
+
+def test_serving_results_equal_alone(torch_mod):
+    torch = torch_mod
+    from paper_1308_4908_amd import Context, Rig, lpa
+
+    ctx = Context(0)
+    frames = make_frames(9, seed0=4200)
+    items, refs = [], []
+    for k, (sensors, raws, p) in enumerate(frames * 2):
+        p = dict(p, storage=["fused", "fp16"][k % 2])
+        rig = Rig(ctx, sensors)
+        refs.append(alone(torch, ctx, rig, [torch.from_numpy(r).cuda() for r in raws], p))
+        items.append((rig, raws, p))
+    _say(f"[gpu] serving {len(items)} mixed frames (pinned host input)")
+    got, res = _serve(torch, ctx, items, host_pinned=True)
+    sizes = []
+    for i, (g, r) in enumerate(zip(got, res)):
+        assert r.status == lpa.OK, i
+        assert r.t_arrival_ns <= r.t_admit_ns <= r.t_start_ns <= r.t_done_ns
+        sizes.append(r.batch_size)
+        assert np.array_equal(g[0], refs[i][0], equal_nan=True), f"frame {i}"
+        assert np.array_equal(g[1], refs[i][1]), f"frame {i}"
+    _say(f"  batch sizes {sizes}")
+    _say("[gpu] serving with pageable host input")
+    got, res = _serve(torch, ctx, items[:5], host_pinned=False)
+    for i, (g, r) in enumerate(zip(got, res)):
+        assert r.status == lpa.OK
+        assert np.array_equal(g[0], refs[i][0], equal_nan=True)
+    for it in items:
+        it[0].close()
+    ctx.close()
+
+
+def test_serving_under_tight_budget(torch_mod):
+    """A budget that holds about two frames: frames queue for admission and all
+    complete correctly."""
+    torch = torch_mod
+    from paper_1308_4908_amd import Context, Rig, lpa
+
+    frames = make_frames(6, seed0=4300)
+    sizes = [sum((r.nbytes + 255) // 256 * 256 for r in raws) for _, raws, _ in frames]
+    budget = int(2.5 * max(sizes)) + 4096
+    ctx = Context(0, hbm_budget_bytes=budget)
+    items, refs = [], []
+    for sensors, raws, p in frames:
+        rig = Rig(ctx, sensors)
+        refs.append(alone(torch, ctx, rig, [torch.from_numpy(r).cuda() for r in raws], p))
+        items.append((rig, raws, p))
+    _say("[gpu] serving under a two-frame budget")
+    got, res = _serve(torch, ctx, items)
+    for i, (g, r) in enumerate(zip(got, res)):
+        assert r.status == lpa.OK
+        # frames in one launch were admitted together, so they fit the budget together
+        assert r.batch_size <= budget // min(sizes)
+        assert np.array_equal(g[0], refs[i][0], equal_nan=True)
+    # a frame larger than the whole budget is rejected with OOM (terminal), not hung
+    small_ctx = Context(0, hbm_budget_bytes=1024)
+    sensors, raws, p = frames[0]
+    rig = Rig(small_ctx, sensors)
+    out = torch.empty((p["out_h"], p["out_w"], 3), device="cuda")
+    t = rig.submit([torch.from_numpy(r).pin_memory() for r in raws], p, out, host=True)
+    small_ctx.drain()
+    assert small_ctx.poll(t).status == lpa.ERR_OOM
+    rig.close()
+    small_ctx.close()
+    for it in items:
+        it[0].close()
+    ctx.close()

@@ -90,7 +90,7 @@ def test_small_full_frame(torch_mod, ctx, storage):
     orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
     st = compare(rgb, smap, orc, sensors, params["order"], gpu_sd=LAST_SD[0])
     _say(f"  stats {st}")
-    assert st["firm_frac"] > 0.99
+    assert st["agree_frac"] > 0.999
 
 
 def test_plain_equals_fused(torch_mod, ctx):
@@ -119,8 +119,7 @@ def test_orders_and_scales(torch_mod, ctx, order, radii):
         orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
         st = compare(rgb, smap, orc, sensors, order, gpu_sd=LAST_SD[0])
         _say(f"  stats {st}")
-        assert st["firm_frac"] > (0.7 if order == 2 else 0.9)
-        assert st["agree_frac"] > 0.99
+        assert st["agree_frac"] > 0.999
 
 
 def test_full_size_sampled(torch_mod, ctx):
@@ -138,8 +137,7 @@ def test_full_size_sampled(torch_mod, ctx):
     m = smap[pix[:, 1], pix[:, 0]]
     st = compare(g, m, orc, sensors, 2, gpu_sd=LAST_SD[0][pix[:, 1], pix[:, 0]])
     _say(f"  stats {st}")
-    assert st["firm_frac"] > 0.7
-    assert st["agree_frac"] > 0.99
+    assert st["agree_frac"] > 0.999
     # every pixel was written and carries a valid code
     assert not np.any(rgb == -12345.0)
     assert not np.any(smap == 0xEE)
@@ -158,14 +156,25 @@ def test_fp16_storage(torch_mod, ctx):
     orc16 = oracle.reconstruct([c[1] for c in conv], [c[0] for c in conv], params, want_fits=True)
     st = compare(rgb, smap, orc16, sensors, 2)
     _say(f"  vs fp16-fed oracle {st}")
+    assert st["agree_frac"] > 0.999
+    # against the exact oracle: storage rounding moves each radiance sample by at
+    # most 2^-12 relative (half an FP16 ulp), so C0 moves by at most about
+    # 2^-12 sum_k |a_k f_k| (plus the weights' share of the same order)
     orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
     both = firm_mask(orc, 2, sensors) & firm_mask(orc16, 2, sensors) & (orc["scale_map"] == orc16["scale_map"])
     y = rgb.reshape(-1, 3)[both]
     ref = orc["rgb"][both]
+    code = orc["scale_map"][both]
     ok = ~np.isnan(ref)
-    e = np.abs(y[ok] - ref[ok]) / np.maximum(np.abs(ref[ok]), floor_of(sensors))
-    _say(f"  vs exact oracle: max {e.max():.3e} p50 {np.median(e):.3e}")
-    assert e.max() <= 2e-3
+    idx = np.nonzero(both)
+    chosen = orc["fits"][idx[0], idx[1], (code & 0xF).astype(int), (code >> 4).astype(int)]
+    scale = np.maximum(np.abs(ref), floor_of(sensors))
+    e = np.abs(y - ref) / scale
+    bound = np.maximum(2e-3 * scale, 4 * 2.0 ** -12 * chosen["l1f"] + 64 * 2.0 ** -24 * chosen["sens_y"])
+    r = (np.abs(y - ref) / (2.0 ** -12 * np.maximum(chosen["l1f"], 1e-300)))[ok]
+    _say(f"  vs exact oracle: max rel {e[ok].max():.3e} p50 {np.median(e[ok]):.3e}; "
+         f"within 2e-3: {np.mean(e[ok] <= 2e-3):.6f}; max |err| / (2^-12 S1) {r.max():.3f}")
+    assert np.all(np.abs(y - ref)[ok] <= bound[ok])
 
 
 def test_resampled_output(torch_mod, ctx):
