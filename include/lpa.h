@@ -77,7 +77,7 @@ enum { LPA_MEM_DEVICE = 0, LPA_MEM_HOST = 1 }; /* where lpa_frame.raw points    
 enum { LPA_STORE_FUSED = 0, LPA_STORE_FP32 = 1, LPA_STORE_FP16 = 2 };
 
 /* lpa_params.flags */
-#define LPA_FLAG_NO_FP64_FALLBACK 0x1u /* never redo ill-conditioned order-2 solves in FP64 */
+#define LPA_FLAG_NO_FP64_FALLBACK 0x1u /* never refine ill-conditioned order-2 solves in FP64 */
 
 /* One sensor of a rig (Sec. 3, Sec. 4, Sec. 6). */
 typedef struct {
@@ -109,7 +109,7 @@ typedef struct {
   double green_ratio;     /* green radius / h scale kappa_G (> 0; 1 = same as R/B)  */
   int32_t storage;        /* LPA_STORE_*                                            */
   double tau_inv;         /* validity threshold; <= 0 selects 1e-5                  */
-  double tau_fp64;        /* order-2 FP64 re-solve below this pivot; <= 0: 1e-3     */
+  double tau_fp64;        /* order-2 solves with a smaller pivot are refined in FP64 (<= 0: 1e-3) */
   uint32_t flags;         /* LPA_FLAG_*                                             */
 } lpa_params;
 

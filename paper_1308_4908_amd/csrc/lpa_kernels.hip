@@ -9,8 +9,8 @@
 // channel and window radius, the CFA sub-lattice points of every sensor inside
 // the radius' bounding box, accumulates the weighted moments of the local
 // polynomial model (Sec. 5.1, eq. wlsqe) in FP32, solves the 1x1/3x3/6x6
-// normal equations in registers (LDL^T of the Jacobi-equilibrated matrix; an
-// FP64 re-solve when an order-2 pivot is small) and runs ICI across radii.
+// normal equations in registers (LDL^T of the Jacobi-equilibrated matrix; FP64
+// iterative refinement when an order-2 pivot is small) and runs ICI across radii.
 //
 // The normal matrix of a polynomial basis has Hankel structure: entry (i, j)
 // is the weighted moment of the monomial phi_i phi_j, so an order-2 fit needs
@@ -216,6 +216,64 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, i
   }
 }
 
+// FP64 refinement of an ill-conditioned order-2 solve.  The FP32 LDL^T of
+// the equilibrated matrix is recomputed here (cheaper than keeping it live),
+// then two steps of iterative refinement with the residual e0 - A g formed in
+// FP64 from the exact FP32 moments bring g = A^-1 e0 to FP64 solve accuracy
+// (the error left is that of the FP32 moments themselves).  C0 = g . b is
+// then summed in FP64.  The variance is recomputed by the caller from g.
+__device__ __forceinline__ void refine_order2(const float* m, const float* b, float* g, float& y) {
+  constexpr int NB = 6;
+  float s[NB], L[NB][NB], iD[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) s[i] = __frsqrt_rn(m[aidx(i, i)]);
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    float d = s[j] * s[j] * m[aidx(j, j)];
+    float D[NB];
+#pragma unroll
+    for (int k = 0; k < j; ++k) D[k] = 1.f / iD[k];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k] * D[k];
+    iD[j] = d > 0.f ? 1.f / d : 0.f;
+#pragma unroll
+    for (int i = j + 1; i < NB; ++i) {
+      float t = s[i] * s[j] * m[aidx(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k] * D[k];
+      L[i][j] = t * iD[j];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    float t[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      double r = (i == 0) ? 1.0 : 0.0;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) r -= (double)m[aidx(i, j)] * (double)g[j];
+      t[i] = (float)r * s[i];
+    }
+    // solve A~ x = t with the FP32 factors, then g += S x
+#pragma unroll
+    for (int i = 1; i < NB; ++i)
+#pragma unroll
+      for (int k = 0; k < i; ++k) t[i] -= L[i][k] * t[k];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) t[i] *= iD[i];
+#pragma unroll
+    for (int i = NB - 1; i >= 0; --i)
+#pragma unroll
+      for (int k = i + 1; k < NB; ++k) t[i] -= L[k][i] * t[k];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) g[i] += s[i] * t[i];
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) acc += (double)g[i] * (double)b[i];
+  y = (float)acc;
+}
+
 // ICI running state of one order (reading: Goldenshluger-Nemirovski rule).
 struct IciState {
   float lo, hi, y, sd;
@@ -258,7 +316,7 @@ __device__ __forceinline__ float2 decode_dn(const SensorK& S, float y) {
   if (!(y < S.sat)) return make_float2(0.f, 0.f);
   const float yb = y - S.black;
   const float var = __builtin_fmaf(S.gain, fmaxf(yb, 0.f), S.read_var) * (S.inv_ge * S.inv_ge);
-  return make_float2(yb * S.inv_ge, 1.f / var);
+  return make_float2(yb * S.inv_ge, __builtin_amdgcn_rcpf(var));
 }
 
 __device__ __forceinline__ float2 decode_f16(const SensorK& S, __half h) {
@@ -266,7 +324,7 @@ __device__ __forceinline__ float2 decode_f16(const SensorK& S, __half h) {
   if (__builtin_isinf(v)) return make_float2(0.f, 0.f);
   const float yb = v * S.norm_decode;  // exact: power-of-two scale
   const float var = __builtin_fmaf(S.gain, fmaxf(yb, 0.f), S.read_var) * (S.inv_ge * S.inv_ge);
-  return make_float2(yb * S.inv_ge, 1.f / var);
+  return make_float2(yb * S.inv_ge, __builtin_amdgcn_rcpf(var));
 }
 
 template <int SRC>
@@ -339,6 +397,46 @@ __device__ __forceinline__ void stage_tile(const LaunchK& K, int u0, int v0, flo
 // where the support is lopsided).
 constexpr float kRhoVarPass = 1e-1f;
 
+// Visits an NB x NB box of sub-lattice points: fully unrolled, so offsets
+// advance by uniform steps and LDS reads use immediate offsets.
+template <int NB, class Fn>
+__device__ __forceinline__ void walk_box_fixed(const float2* p0, int row_step, float c0x, float c0y,
+                                               float sax, float say, float sbx, float sby, Fn& fn) {
+  float rx = c0x, ry = c0y;
+#pragma unroll
+  for (int jj = 0; jj < NB; ++jj) {
+    const float2* prow = p0 + jj * row_step;
+    float dx = rx, dy = ry;
+#pragma unroll
+    for (int ii = 0; ii < NB; ++ii) {
+      const float2 sm = prow[2 * ii];
+      fn(dx, dy, sm.x, sm.y);
+      dx += sax;
+      dy += say;
+    }
+    rx += sbx;
+    ry += sby;
+  }
+}
+
+template <class Fn>
+__device__ __forceinline__ void walk_box_any(const float2* p0, int row_step, int nx, int ny, float c0x, float c0y,
+                                             float sax, float say, float sbx, float sby, Fn& fn) {
+  float rx = c0x, ry = c0y;
+  for (int jj = 0; jj < ny; ++jj) {
+    const float2* prow = p0 + jj * row_step;
+    float dx = rx, dy = ry;
+    for (int ii = 0; ii < nx; ++ii) {
+      const float2 sm = prow[2 * ii];
+      fn(dx, dy, sm.x, sm.y);
+      dx += sax;
+      dy += say;
+    }
+    rx += sbx;
+    ry += sby;
+  }
+}
+
 // Calls fn(dx, dy, f, iv) for every CFA sample of channel c inside the box of
 // radius index m around (Xj, Yj), over all sensors (scaled offsets).
 template <class Fn>
@@ -361,6 +459,7 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
     const float sax = (float)(2.0 * S.fwd[0]) * cs, say = (float)(2.0 * S.fwd[3]) * cs;
     const float sbx = (float)(2.0 * S.fwd[1]) * cs, sby = (float)(2.0 * S.fwd[4]) * cs;
     const float2* plane = lds + S.lds_off;
+    const int row_step = 2 * R.w;
     const int nsub = S.sub_n[c];
     for (int q = 0; q < nsub; ++q) {
       const int ox = S.sub_ox[c][q], oy = S.sub_oy[c][q];
@@ -373,16 +472,13 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
       const float c0x = (float)((Xb - Xj) * cs);
       const float c0y = (float)((Yb - Yj) * cs);
       const float2* p0 = plane + (yb - R.y0) * R.w + (xb - R.x0);
-      for (int jj = 0; jj < ny; ++jj) {
-        const float rx = __builtin_fmaf((float)jj, sbx, c0x);
-        const float ry = __builtin_fmaf((float)jj, sby, c0y);
-        const float2* prow = p0 + 2 * jj * R.w;
-        for (int ii = 0; ii < nx; ++ii) {
-          const float dx = __builtin_fmaf((float)ii, sax, rx);
-          const float dy = __builtin_fmaf((float)ii, say, ry);
-          const float2 sm = prow[2 * ii];
-          fn(dx, dy, sm.x, sm.y);
-        }
+      switch (nx == ny ? nx : 0) {
+        case 1: walk_box_fixed<1>(p0, row_step, c0x, c0y, sax, say, sbx, sby, fn); break;
+        case 2: walk_box_fixed<2>(p0, row_step, c0x, c0y, sax, say, sbx, sby, fn); break;
+        case 3: walk_box_fixed<3>(p0, row_step, c0x, c0y, sax, say, sbx, sby, fn); break;
+        case 4: walk_box_fixed<4>(p0, row_step, c0x, c0y, sax, say, sbx, sby, fn); break;
+        case 5: walk_box_fixed<5>(p0, row_step, c0x, c0y, sax, say, sbx, sby, fn); break;
+        default: walk_box_any(p0, row_step, nx, ny, c0x, c0y, sax, say, sbx, sby, fn); break;
       }
     }
   }
@@ -407,34 +503,16 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
       const float eedge = K.sc[m].e_edge[cls];
       Acc<ORDER, ICI> a;
       acc_zero(a);
-      walk_support(K, lds, regs, Xj, Yj, c, cls, m, [&](float dx, float dy, float f, float iv) {
+      auto accumulate = [&](float dx, float dy, float f, float iv) {
         acc_sample<ORDER, ICI>(a, dx, dy, f, iv, kexp, eedge);
-      });
+      };
+      walk_support(K, lds, regs, Xj, Yj, c, cls, m, accumulate);
 
       Fits<float, ORDER> fr;
       solve_fits<float, ORDER, ICI>(a.m, a.b, a.B, a.n, K.tau_inv, fr);
       if constexpr (ORDER == 2) {
-        // FP64 re-solve of ill-conditioned order-2 systems from the FP32 moments
-        if (K.use_fp64 && a.n >= 6 && fr.rho[2] < K.tau_fp64 && fr.rho[0] > 0.f) {
-          double md[n_mom<ORDER>()], bd[n_basis<ORDER>()], Bd[ICI ? n_mom<ORDER>() : 1];
-#pragma unroll
-          for (int k = 0; k < n_mom<ORDER>(); ++k) md[k] = a.m[k];
-#pragma unroll
-          for (int k = 0; k < n_basis<ORDER>(); ++k) bd[k] = a.b[k];
-#pragma unroll
-          for (int k = 0; k < (ICI ? n_mom<ORDER>() : 1); ++k) Bd[k] = a.B[k];
-          Fits<double, ORDER> fd;
-          solve_fits<double, ORDER, ICI>(md, bd, Bd, a.n, (double)K.tau_inv, fd);
-#pragma unroll
-          for (int o = 0; o <= ORDER; ++o) {
-            fr.y[o] = (float)fd.y[o];
-            fr.v[o] = (float)fd.v[o];
-            fr.ok[o] = fd.ok[o];
-            fr.rho[o] = (float)fd.rho[o];
-#pragma unroll
-            for (int i = 0; i < n_basis<ORDER>(); ++i) fr.g[o][i] = (float)fd.g[o][i];
-          }
-        }
+        // ill-conditioned order-2 solves: FP64 iterative refinement
+        if (K.use_fp64 && fr.ok[2] && fr.rho[2] < K.tau_fp64) refine_order2(a.m, a.b, fr.g[2], fr.y[2]);
       }
       if constexpr (ICI && ORDER >= 1) {
         // Variance of ill-conditioned fits from the samples (positive terms).
@@ -445,7 +523,7 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
           float vs[ORDER + 1];
 #pragma unroll
           for (int o = 0; o <= ORDER; ++o) vs[o] = 0.f;
-          walk_support(K, lds, regs, Xj, Yj, c, cls, m, [&](float dx, float dy, float f, float iv) {
+          auto var_term = [&](float dx, float dy, float f, float iv) {
             (void)f;
             const float x2 = dx * dx, y2 = dy * dy;
             const float kw = fmaxf(__builtin_amdgcn_exp2f((x2 + y2) * kexp) - eedge, 0.f);
@@ -459,7 +537,8 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
               for (int i = 1; i < nb_tab[o]; ++i) t = __builtin_fmaf(fr.g[o][i], phi[i], t);
               vs[o] = __builtin_fmaf(t * t, w2, vs[o]);
             }
-          });
+          };
+          walk_support(K, lds, regs, Xj, Yj, c, cls, m, var_term);
 #pragma unroll
           for (int o = 1; o <= ORDER; ++o)
             if (fr.rho[o] < kRhoVarPass) fr.v[o] = vs[o];
