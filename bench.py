@@ -9,10 +9,16 @@ log-uniform over [1e-2, 1e4]); inputs are resident in HBM before timing.
 
 Reported: the optimised form (raw samples decoded straight into LDS by the
 fit kernel, tuned tile) as `value`; the plain per-frame FP32 form (FP32
-pre-pass planes + fixed tile) beside it; the roofline of the fit kernel; the
-FP64 oracle on a bounded band of the same frame on the host cores.
+pre-pass planes + fixed 16x16 tile) beside it; the roofline of the fit
+kernel; the FP64 oracle on a bounded band of the same frame on the host cores.
+Two more legs run on frames cut from the same capture (crops to 1280x720 /
+1920x1080 / 2048x2048 and subsets of 2-4 sensors, so nothing new has to be
+generated): a batch of 64 mixed frames (orders 1 and 2) in one persistent
+graph launch, against the same frames one plain launch each; and a served run
+of 8 cameras with Poisson arrivals at 30 fps each (mixed 1080p / 4 Mpix,
+3-4 sensors, order 2, FP16 storage) reporting p50 / p99 frame latency.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--serve-seconds S]
 """
 from __future__ import annotations
 
@@ -91,16 +97,140 @@ def cpu_baseline(sensors, raws, params, rows: int):
                       f"{dt:.1f} s single-threaded FP64"}
 
 
+def cut_frame(sensors, raws, keep, w, h):
+    """A smaller frame cut from the capture: sensors `keep`, top-left w x h of
+    each plane (pixel coordinates, hence the affines, are unchanged)."""
+    ss = [dict(sensors[i], width=w, height=h) for i in keep]
+    rr = [raws[i][:h, :w] for i in keep]
+    return ss, rr
+
+
+BATCH_SHAPES = [(1280, 720), (1920, 1080), (2048, 2048)]
+SUBSETS = {2: [0, 2], 3: [0, 1, 3], 4: [0, 1, 2, 3]}
+
+
+def batch_leg(torch, ctx, Rig, sensors, raws, configs, n_frames, storage, reps=3):
+    """n_frames mixed frames in one persistent launch vs one plain launch each."""
+    rng = __import__("numpy").random.default_rng(4000)
+    frames = []
+    for i in range(n_frames):
+        w, h = BATCH_SHAPES[int(rng.integers(0, 3))]
+        ns = int(rng.integers(2, 5))
+        order = int(rng.integers(1, 3))
+        ss, rr = cut_frame(sensors, raws, SUBSETS[ns], w, h)
+        rig = Rig(ctx, ss)
+        dev = [torch.from_numpy(r.copy()).cuda() for r in rr]
+        p = configs.lpa_params(w, h, order, [1.0, 2.0, 3.0, 4.0], storage=storage)
+        out = torch.empty((h, w, 3), device="cuda")
+        frames.append((rig, dev, p, out))
+    n_px = sum(p["out_w"] * p["out_h"] for _, _, p, _ in frames)
+    rigs = [f[0] for f in frames]
+    devs = [f[1] for f in frames]
+    ps = [f[2] for f in frames]
+    outs = [f[3] for f in frames]
+    ctx.reconstruct_batch(rigs, devs, ps, outs)  # capture the graph
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.reconstruct_batch(rigs, devs, ps, outs)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / reps
+    for rig, dev, p, out in frames:
+        rig.reconstruct(dev, p, out, plain=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for rig, dev, p, out in frames:
+        rig.reconstruct(dev, p, out, plain=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1)
+    for r in rigs:
+        r.close()
+    return {"frames": n_frames, "mpix": round(n_px / 1e6, 2), "storage": storage,
+            "batched_mpix_s": round(n_px / (ms_batch * 1e-3) / 1e6, 3), "batch_ms": round(ms_batch, 3),
+            "plain_per_frame_mpix_s": round(n_px / (ms_plain * 1e-3) / 1e6, 3),
+            "speedup": round(ms_plain / ms_batch, 3)}
+
+
+def serve_leg(torch, ctx, Rig, sensors, raws, configs, seconds, n_cameras=8, rate=30.0):
+    """Cameras with Poisson arrivals; frames submitted from pinned host memory."""
+    import numpy as np
+
+    cams = []
+    for c in range(n_cameras):
+        spec = configs.camera_spec(c)
+        w, h = spec["width"], spec["height"]
+        ss, rr = cut_frame(sensors, raws, SUBSETS[spec["n_sensors"]], w, h)
+        rig = Rig(ctx, ss)
+        host = [torch.from_numpy(np.ascontiguousarray(r)).pin_memory() for r in rr]
+        p = configs.lpa_params(w, h, 2, [1.0, 2.0, 3.0, 4.0], storage="fp16")
+        outs = [torch.empty((h, w, 3), device="cuda") for _ in range(6)]
+        arr = configs.poisson_arrivals(c, rate, seconds)
+        cams.append((rig, host, p, outs, arr))
+    events = sorted((t, c) for c, cam in enumerate(cams) for t in cam[4])
+    tickets = []
+    t0 = time.monotonic_ns()
+    k = [0] * n_cameras
+    for t, c in events:
+        due = t0 + int(t * 1e9)
+        while True:
+            now = time.monotonic_ns()
+            if now >= due:
+                break
+            time.sleep(min(0.0005, (due - now) / 1e9))
+        rig, host, p, outs, _ = cams[c]
+        out = outs[k[c] % len(outs)]
+        k[c] += 1
+        tk = None
+        while tk is None:
+            tk = rig.submit(host, p, out, arrival_ns=due, host=True)
+        tickets.append((tk, p["out_w"] * p["out_h"]))
+    ctx.drain()
+    t_end = time.monotonic_ns()
+    lat, px, done_last = [], 0, t0
+    for tk, npx in tickets:
+        r = ctx.poll(tk)
+        if r.status == 0:
+            lat.append((r.t_done_ns - r.t_arrival_ns) / 1e6)
+            px += npx
+            done_last = max(done_last, r.t_done_ns)
+    for cam in cams:
+        cam[0].close()
+    lat = np.asarray(lat)
+    return {"cameras": n_cameras, "seconds": seconds, "frames": len(tickets), "completed": int(lat.size),
+            "served_mpix_s": round(px / ((done_last - t0) / 1e9) / 1e6, 2),
+            "latency_p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "latency_p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "latency_max_ms": round(float(lat.max()), 3), "drain_ms": round((t_end - t0) / 1e6 - seconds * 1e3, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=2048)
-    ap.add_argument("--cpu-rows", type=int, default=48)
+    ap.add_argument("--cpu-rows", type=int, default=160)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--batch-frames", type=int, default=64)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe_mib:
+        import torch
+
+        n = args.copy_probe_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "launches": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X "
               "(multi-GPU sharding is described in DESIGN.md but not run).", file=sys.stderr)
@@ -141,6 +271,10 @@ def main():
         per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
         return sum(per) / steps, wall, per
 
+    print("[bench] tuning the launch shape for this frame class", file=sys.stderr, flush=True)
+    tr = rig.autotune(dev, params, out, reps=3)
+    tuned = {"tile": f"{tr.tile_w}x{tr.tile_h}", "waves_per_simd_budget": 4 if tr.occupancy == 4 else 3,
+             "candidates": tr.n_candidates, "ms_best": round(tr.ms_best, 4), "ms_default": round(tr.ms_default, 4)}
     print("[bench] timing the optimised form", file=sys.stderr, flush=True)
     ms, wall, per = timed(False, args.steps, args.warmup)
     value = n_px / (ms * 1e-3) / 1e6
@@ -157,22 +291,35 @@ def main():
             "kernel": "fit_kernel<order 2, ICI, raw uint16>",
             "flop_per_launch": round(flops), "flop_per_pixel": round(flop_px, 1),
             "samples_per_pixel": round(samples_px, 2), "sample_scale_updates_per_pixel": round(updates_px, 2)}
+    batched = None
+    if args.batch_frames > 0 and size == 2048:
+        batched = {}
+        for st in ("fused", "fp16"):
+            print(f"[bench] batched leg ({args.batch_frames} mixed frames, {st})", file=sys.stderr, flush=True)
+            batched[st] = batch_leg(torch, ctx, Rig, sensors, raws, configs, args.batch_frames, st)
+    served = None
+    if args.serve_seconds > 0 and size == 2048:
+        print(f"[bench] served leg ({args.serve_seconds} s, 8 cameras)", file=sys.stderr, flush=True)
+        served = serve_leg(torch, ctx, Rig, sensors, raws, configs, args.serve_seconds)
     cpu = None
     if not args.no_cpu:
         print("[bench] timing the FP64 oracle on a band", file=sys.stderr, flush=True)
         cpu = cpu_baseline(sensors, raws, params, args.cpu_rows)
     line = {
-        "metric": "HDR output Mpixel/s at 4 Mpix order-2 ICI",
+        "metric": "HDR output Mpixel/s at 4 Mpix order-2 ICI vs plain FP32; p99 frame latency",
         "value": round(value, 3), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"4 x {size}x{size} raw uint16 12-bit RGGB, exposures 1/1/4/1/16/1/64, "
                                f"order-2 LPA, ICI radii {{1,2,3,4}} Gamma 2, {size}x{size} RGB fp32 output",
-                   "form": "fused raw decode + fit, one launch per frame", "frames_per_step": 1},
+                   "form": "fused raw decode + fit, one launch per frame, tuned launch shape",
+                   "frames_per_step": 1, "tuned": tuned},
         "plain_fp32": plain,
         "speedup_vs_plain": round(value / plain["value"], 3) if plain else None,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
         "wall_s_timed": round(wall, 3),
         "ms_per_step_min": round(min(per), 4), "ms_per_step_max": round(max(per), 4),
     }

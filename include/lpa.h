@@ -198,6 +198,24 @@ lpa_status lpa_poll(lpa_ctx* ctx, uint64_t ticket, lpa_result* out);
 /* Block until every submitted frame is finished. */
 lpa_status lpa_drain(lpa_ctx* ctx);
 
+/* Autotuning (launch shape only; results never depend on it).  Candidates:
+ * tile shapes 16x16, 32x8, 8x32, 64x4 output pixels (256 lanes; a wavefront
+ * covers 16x4, 32x2, 8x8 or 64x1 pixels) times two register budgets for
+ * order-2 fits (3 or 4 waves per SIMD).  Each candidate is launched on the
+ * given frame `reps` times on `hip_stream` (writing `out`), timed with HIP
+ * events; the fastest becomes the choice for every frame of the same class
+ * (order, radii, sensor count, storage, output zoom) in this context.
+ * Blocks until the timing is done. */
+typedef struct {
+  int32_t tile_w, tile_h, occupancy, n_candidates;
+  double ms_best, ms_default; /* per launch; default = 16x16, default registers */
+} lpa_tune_result;
+lpa_status lpa_autotune(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
+                        const lpa_output* out, void* hip_stream, int32_t reps, lpa_tune_result* result);
+/* Persist / restore the context's tuning choices (small JSON file). */
+lpa_status lpa_tuner_save(lpa_ctx* ctx, const char* path);
+lpa_status lpa_tuner_load(lpa_ctx* ctx, const char* path);
+
 /* Thread-local message of the last non-OK status returned on this thread. */
 const char* lpa_last_error(void);
 

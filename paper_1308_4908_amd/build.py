@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblpa.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["lpa_kernels.hip", "lpa_api.cpp", "lpa_batch.cpp", "lpa_serve.cpp"]
+SOURCES = ["lpa_kernels.hip", "lpa_api.cpp", "lpa_batch.cpp", "lpa_serve.cpp", "lpa_tune.cpp"]
 ARCH = os.environ.get("LPA_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

@@ -358,11 +358,17 @@ lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_para
       pitches[s] = 0;
     }
   }
-  if (!plain) ctx->tuner.choose(Tuner::key_of(rig, R, src_kind), &tw, &th);
+  TuneChoice tc;
+  if (!plain) {
+    tc = ctx->tuner.choose(Tuner::key_of(rig, R, src_kind));
+    tw = tc.tile_w;
+    th = tc.tile_h;
+  }
   LaunchK K;
   st = plain ? build_launch(rig, R, out, src_kind, srcs, pitches, 16, 16, &K)
              : build_launch_fit(rig, R, out, src_kind, srcs, pitches, tw, th, &K);
   if (st != LPA_OK) return st;
+  K.occupancy = tc.occupancy;
 
   if (storage != LPA_STORE_FUSED) {
     st = run_prepass(rig, frame, storage == LPA_STORE_FP16, hs, planes, plane_bytes, srcs, pitches);

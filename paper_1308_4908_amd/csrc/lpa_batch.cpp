@@ -55,8 +55,8 @@ lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_f
       srcs[s] = frames[i].raw[s];
       pitches[s] = frames[i].row_pitch_bytes[s];
     }
-    int tw = 16, th = 16;
-    ctx->tuner.choose(Tuner::key_of(rigs[i], Rs[i], sk), &tw, &th);
+    const TuneChoice tc = ctx->tuner.choose(Tuner::key_of(rigs[i], Rs[i], sk));
+    int tw = tc.tile_w, th = tc.tile_h;
     lpa_status st = build_launch(rigs[i], Rs[i], &outs[i], sk, srcs, pitches, tw, th, &(*ks)[i]);
     if (st == LPA_ERR_UNSUPPORTED && tw * th == 256)
       for (const int* t : {(const int[]){16, 16}, (const int[]){32, 8}, (const int[]){64, 4}}) {

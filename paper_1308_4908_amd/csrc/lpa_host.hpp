@@ -45,7 +45,7 @@ struct TuneKey {
 };
 
 struct TuneChoice {
-  int tile_w = 16, tile_h = 16;
+  int tile_w = 16, tile_h = 16, occupancy = 0;
 };
 
 struct lpa_rig_fwd;
@@ -55,15 +55,10 @@ class Tuner {
   // Tile shape for a frame's class: the measured best if the class was tuned,
   // else 16 x 16.  Every candidate has 256 lanes, so batched launches can mix
   // classes.
-  void choose(const TuneKey& k, int* tw, int* th) {
+  TuneChoice choose(const TuneKey& k) {
     TuneChoice c;
-    if (lookup(k, &c)) {
-      *tw = c.tile_w;
-      *th = c.tile_h;
-    } else {
-      *tw = 16;
-      *th = 16;
-    }
+    if (!lookup(k, &c)) c = TuneChoice();
+    return c;
   }
   void set(const TuneKey& k, TuneChoice c) {
     std::lock_guard<std::mutex> g(mu_);

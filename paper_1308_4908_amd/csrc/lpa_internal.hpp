@@ -61,6 +61,8 @@ struct LaunchK {
   int32_t use_fp64;
   int32_t lds_floats2;      // float2 elements of LDS this launch uses
   int32_t need_var;         // estimator variance needed (several radii or an sd map)
+  int32_t occupancy;        // 0: default register budget; 4: compiled for 4 waves/SIMD (order 2)
+  int32_t pad2_;
   float* rgb;
   int64_t rgb_pitch;        // bytes
   uint8_t* map;

@@ -605,6 +605,16 @@ __global__ void __launch_bounds__(256) fit_kernel(const LaunchK K) {
   process_tile<ORDER, ICI, SRC>(K, blockIdx.x, lds, regs);
 }
 
+// Same kernel compiled for 4 waves per SIMD (<= 128 VGPRs, a few spills in
+// cold paths); the tuner picks whichever is faster for a frame's class.
+template <int ORDER, bool ICI, int SRC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+fit_kernel_occ4(const LaunchK K) {
+  extern __shared__ float2 lds[];
+  __shared__ Region regs[kMaxSensors];
+  process_tile<ORDER, ICI, SRC>(K, blockIdx.x, lds, regs);
+}
+
 // Persistent form: workgroups take tiles from a device counter until the
 // queue is exhausted; every workgroup reaches the exit test each round.  The
 // frame's order and single/multi-radius class select the fit code per tile
@@ -676,15 +686,26 @@ using namespace lpa;
 namespace {
 constexpr int kMaxLdsBytes = 64 * 1024;
 
+template <int ORDER, bool ICI, int SRC>
+void launch_fit_one(const LaunchK& K, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+  if constexpr (ORDER == 2) {
+    if (K.occupancy == 4) {
+      fit_kernel_occ4<ORDER, ICI, SRC><<<grid, block, lds, st>>>(K);
+      return;
+    }
+  }
+  fit_kernel<ORDER, ICI, SRC><<<grid, block, lds, st>>>(K);
+}
+
 template <int ORDER, bool ICI>
 int launch_fit_src(const LaunchK& K, hipStream_t st) {
   const dim3 grid(K.tiles_x * K.tiles_y), block(K.tile_w * K.tile_h);
   const size_t lds = (size_t)K.lds_floats2 * sizeof(float2);
   switch (K.src_kind) {
-    case SRC_RAW_U16: fit_kernel<ORDER, ICI, SRC_RAW_U16><<<grid, block, lds, st>>>(K); break;
-    case SRC_RAW_F32: fit_kernel<ORDER, ICI, SRC_RAW_F32><<<grid, block, lds, st>>>(K); break;
-    case SRC_PLANE_F32: fit_kernel<ORDER, ICI, SRC_PLANE_F32><<<grid, block, lds, st>>>(K); break;
-    case SRC_PLANE_F16: fit_kernel<ORDER, ICI, SRC_PLANE_F16><<<grid, block, lds, st>>>(K); break;
+    case SRC_RAW_U16: launch_fit_one<ORDER, ICI, SRC_RAW_U16>(K, grid, block, lds, st); break;
+    case SRC_RAW_F32: launch_fit_one<ORDER, ICI, SRC_RAW_F32>(K, grid, block, lds, st); break;
+    case SRC_PLANE_F32: launch_fit_one<ORDER, ICI, SRC_PLANE_F32>(K, grid, block, lds, st); break;
+    case SRC_PLANE_F16: launch_fit_one<ORDER, ICI, SRC_PLANE_F16>(K, grid, block, lds, st); break;
     default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -2;

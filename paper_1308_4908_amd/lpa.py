@@ -74,6 +74,13 @@ class Output(ctypes.Structure):
     ]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [
+        ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("occupancy", ctypes.c_int32),
+        ("n_candidates", ctypes.c_int32), ("ms_best", ctypes.c_double), ("ms_default", ctypes.c_double),
+    ]
+
+
 class Result(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("t_arrival_ns", ctypes.c_int64),
@@ -101,6 +108,11 @@ SIGNATURES = {
                                     ctypes.POINTER(Output), ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]),
     "lpa_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Result)]),
     "lpa_drain": (ctypes.c_int32, [ctypes.c_void_p]),
+    "lpa_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Frame), ctypes.POINTER(Params),
+                                      ctypes.POINTER(Output), ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.POINTER(TuneResult)]),
+    "lpa_tuner_save": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_char_p]),
+    "lpa_tuner_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_char_p]),
     "lpa_last_error": (ctypes.c_char_p, []),
 }
 
@@ -149,6 +161,9 @@ lpa_reconstruct_batch = _c("lpa_reconstruct_batch")
 lpa_submit = _c("lpa_submit")
 lpa_poll = _c("lpa_poll")
 lpa_drain = _c("lpa_drain")
+lpa_autotune = _c("lpa_autotune")
+lpa_tuner_save = _c("lpa_tuner_save")
+lpa_tuner_load = _c("lpa_tuner_load")
 lpa_last_error = _c("lpa_last_error")
 
 
@@ -295,6 +310,12 @@ class Context:
         ou = (Output * n)(*[output_struct(o, m) for o, m in zip(outs, maps)])
         check(lpa_reconstruct_batch(self.handle, n, rig_arr, fr, pr, ou, _stream_handle(stream)))
 
+    def tuner_save(self, path: str):
+        check(lpa_tuner_save(self.handle, path.encode()))
+
+    def tuner_load(self, path: str):
+        check(lpa_tuner_load(self.handle, path.encode()))
+
     def poll(self, ticket: int) -> Result:
         r = Result()
         check(lpa_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(r)), ok=(OK, NOT_READY))
@@ -335,6 +356,16 @@ class Rig:
         ou = output_struct(out, scale_map, sd_map)
         fn = lpa_reconstruct_plain if plain else lpa_reconstruct
         check(fn(self.handle, ctypes.byref(fr), ctypes.byref(pr), ctypes.byref(ou), _stream_handle(stream)))
+
+    def autotune(self, raws, params: dict, out, reps: int = 3, stream=None) -> TuneResult:
+        """Time every launch-shape candidate on this frame; keep the fastest for its class."""
+        fr = frame_struct(raws)
+        pr = params_struct(params)
+        ou = output_struct(out)
+        res = TuneResult()
+        check(lpa_autotune(self.handle, ctypes.byref(fr), ctypes.byref(pr), ctypes.byref(ou),
+                           _stream_handle(stream), int(reps), ctypes.byref(res)))
+        return res
 
     def submit(self, raws, params: dict, out, scale_map=None, arrival_ns: int = 0, host: bool = False):
         fr = frame_struct(raws, on_device=not host)

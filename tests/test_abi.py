@@ -38,16 +38,17 @@ def test_struct_layouts_match_header():
 
     from paper_1308_4908_amd import lpa
 
-    src = '#include "lpa.h"\n#include <stdio.h>\nint main(void){printf("%zu %zu %zu %zu %zu %zu\\n",' \
+    src = '#include "lpa.h"\n#include <stdio.h>\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n",' \
           'sizeof(lpa_sensor_desc),sizeof(lpa_rig_desc),sizeof(lpa_params),sizeof(lpa_frame),' \
-          'sizeof(lpa_output),sizeof(lpa_result));return 0;}\n'
+          'sizeof(lpa_output),sizeof(lpa_result),sizeof(lpa_tune_result));return 0;}\n'
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
         exe = os.path.join(d, "s")
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         sizes = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
-    mine = [ctypes.sizeof(t) for t in (lpa.SensorDesc, lpa.RigDesc, lpa.Params, lpa.Frame, lpa.Output, lpa.Result)]
+    mine = [ctypes.sizeof(t) for t in (lpa.SensorDesc, lpa.RigDesc, lpa.Params, lpa.Frame, lpa.Output, lpa.Result,
+                                       lpa.TuneResult)]
     assert sizes == mine
 
 
@@ -74,3 +75,6 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lpa.lpa_create_rig(None, None, None) == lpa.ERR_INVALID_ARG
     assert lpa.lpa_reconstruct(None, None, None, None, None) == lpa.ERR_INVALID_ARG
     assert lpa.lpa_poll(None, 0, None) == lpa.ERR_INVALID_ARG
+    assert lpa.lpa_autotune(None, None, None, None, None, 1, None) == lpa.ERR_INVALID_ARG
+    assert lpa.lpa_tuner_save(None, None) == lpa.ERR_INVALID_ARG
+    assert lpa.lpa_tuner_load(None, None) == lpa.ERR_INVALID_ARG

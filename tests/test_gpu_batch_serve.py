@@ -184,3 +184,36 @@ def test_serving_under_tight_budget(torch_mod):
     for it in items:
         it[0].close()
     ctx.close()
+
+
+def test_autotune_keeps_results_and_persists(torch_mod, tmp_path):
+    """The tuner only changes the launch shape: tuned output is bit-identical;
+    its choices round-trip through the JSON file."""
+    torch = torch_mod
+    from paper_1308_4908_amd import Context, Rig
+
+    sensors, raws, p = make_frames(2, seed0=4400)[1]  # an order-2 frame
+    assert p["order"] == 2
+    ctx = Context(0)
+    rig = Rig(ctx, sensors)
+    dev = [torch.from_numpy(r).cuda() for r in raws]
+    ref = alone(torch, ctx, rig, dev, p)
+    out = torch.empty((p["out_h"], p["out_w"], 3), device="cuda")
+    _say("[gpu] autotune")
+    res = rig.autotune(dev, p, out, reps=2)
+    assert res.n_candidates == 8 and res.tile_w * res.tile_h == 256
+    got = alone(torch, ctx, rig, dev, p)
+    assert np.array_equal(got[0], ref[0], equal_nan=True) and np.array_equal(got[1], ref[1])
+    path = str(tmp_path / "tune.json")
+    ctx.tuner_save(path)
+    ctx2 = Context(0)
+    ctx2.tuner_load(path)
+    rig2 = Rig(ctx2, sensors)
+    got2 = alone(torch, ctx2, rig2, dev, p)
+    assert np.array_equal(got2[0], ref[0], equal_nan=True)
+    text = open(path).read()
+    assert f'"tile_w": {res.tile_w}' in text
+    rig2.close()
+    ctx2.close()
+    rig.close()
+    ctx.close()
