@@ -391,11 +391,11 @@ __device__ __forceinline__ void stage_tile(const LaunchK& K, int u0, int v0, flo
 // Per-pixel fit of one tile.  All loop bounds are uniform across the wave.
 // ---------------------------------------------------------------------------
 
-// Below this equilibrated pivot the variance of a fit is recomputed from the
-// samples as sum_k (g . phi_k)^2 K_k w_k (all terms positive) instead of the
-// moment form g^T B g, whose FP32 rounding grows like u / rho^2 (and faster
-// where the support is lopsided).
-constexpr float kRhoVarPass = 1e-1f;
+// Fits whose equilibrated pivot is below tau_fp64 (ill-conditioned) get their
+// variance recomputed from the samples as sum_k (g . phi_k)^2 K_k w_k (all
+// terms positive) instead of the moment form g^T B g.  Above it both forms
+// carry ~1e-4 relative error or less in FP32; below it the moment form's
+// cancellation grows quickly.
 
 // Visits an NB x NB box of sub-lattice points: fully unrolled, so offsets
 // advance by uniform steps and LDS reads use immediate offsets.
@@ -518,7 +518,7 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
         // Variance of ill-conditioned fits from the samples (positive terms).
         bool need = false;
 #pragma unroll
-        for (int o = 1; o <= ORDER; ++o) need = need || (fr.ok[o] && fr.rho[o] < kRhoVarPass);
+        for (int o = 1; o <= ORDER; ++o) need = need || (fr.ok[o] && fr.rho[o] < K.tau_fp64);
         if (need) {
           float vs[ORDER + 1];
 #pragma unroll
@@ -541,7 +541,7 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
           walk_support(K, lds, regs, Xj, Yj, c, cls, m, var_term);
 #pragma unroll
           for (int o = 1; o <= ORDER; ++o)
-            if (fr.rho[o] < kRhoVarPass) fr.v[o] = vs[o];
+            if (fr.rho[o] < K.tau_fp64) fr.v[o] = vs[o];
         }
       }
 #pragma unroll
