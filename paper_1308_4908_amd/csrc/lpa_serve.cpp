@@ -123,6 +123,9 @@ struct Scheduler {
     ctx->used.fetch_sub(r->reserved);
     delete r;
     --pending;
+    // every terminal path (completion, rejection at admission, launch failure)
+    // must wake lpa_drain, which waits for pending == 0
+    cv_done.notify_all();
   }
 
   // Bytes a frame occupies on the device while in flight.
