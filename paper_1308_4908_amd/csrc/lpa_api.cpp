@@ -62,6 +62,12 @@ lpa_status validate_rig(const lpa_rig_desc* d) {
     if (!(S.gain > 0) || !std::isfinite(S.gain)) return set_error(LPA_ERR_INVALID_ARG, "sensor %d: gain must be > 0", s);
     if (!(S.read_sigma > 0) || !std::isfinite(S.read_sigma))
       return set_error(LPA_ERR_INVALID_ARG, "sensor %d: read_sigma must be > 0", s);
+    {
+      // the FP32 inverse variance of a dark sample must be finite
+      const double v = S.read_sigma * S.read_sigma / (S.gain * S.exposure * S.gain * S.exposure);
+      if (!(v > 1e-30) || !(v < 1e30))
+        return set_error(LPA_ERR_INVALID_ARG, "sensor %d: read noise variance out of FP32 range", s);
+    }
     if (!std::isfinite(S.black_level) || !(S.saturation > S.black_level))
       return set_error(LPA_ERR_INVALID_ARG, "sensor %d: saturation must exceed black_level", s);
   }

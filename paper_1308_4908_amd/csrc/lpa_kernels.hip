@@ -41,7 +41,6 @@ struct Acc {
   float m[n_mom<ORDER>()];            // sum w * monomial
   float b[n_basis<ORDER>()];          // sum w * f * phi
   float B[ICI ? n_mom<ORDER>() : 1];  // sum K w * monomial (variance of C0)
-  int n;                              // samples with positive weight
 };
 
 template <int ORDER, bool ICI>
@@ -52,7 +51,6 @@ __device__ __forceinline__ void acc_zero(Acc<ORDER, ICI>& a) {
   for (int k = 0; k < n_basis<ORDER>(); ++k) a.b[k] = 0.f;
 #pragma unroll
   for (int k = 0; k < (ICI ? n_mom<ORDER>() : 1); ++k) a.B[k] = 0.f;
-  a.n = 0;
 }
 
 // One sample: scaled offset (dx, dy), radiance f, inverse variance iv.
@@ -86,7 +84,6 @@ __device__ __forceinline__ void acc_sample(Acc<ORDER, ICI>& a, float dx, float d
   // Gaussian window shifted to vanish at the radius; zero outside the disc.
   const float kw = fmaxf(__builtin_amdgcn_exp2f(r2 * k_exp) - e_edge, 0.f);
   const float w = kw * iv;
-  a.n += (w > 0.f) ? 1 : 0;
   const float wf = w * f;
   a.m[0] += w;
 #pragma unroll
@@ -121,14 +118,19 @@ struct Fits {
 
 template <typename T>
 __device__ __forceinline__ T rsqrt_t(T x);
+template <typename T>
+__device__ __forceinline__ T rcp_t(T x);
 template <>
-__device__ __forceinline__ float rsqrt_t<float>(float x) { return __frsqrt_rn(x); }
+__device__ __forceinline__ float rcp_t<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double rcp_t<double>(double x) { return 1.0 / x; }
+template <>
+__device__ __forceinline__ float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <>
 __device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
 
 template <typename T, int ORDER, bool ICI>
-__device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, int n, T tau,
-                                           Fits<T, ORDER>& out) {
+__device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T tau, Fits<T, ORDER>& out) {
   constexpr int NB = n_basis<ORDER>();
   T s[NB];
   bool dok[NB];
@@ -146,7 +148,7 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, i
 #pragma unroll
     for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k] * D[k];
     D[j] = d;
-    iD[j] = d > T(0) ? T(1) / d : T(0);
+    iD[j] = d > T(0) ? rcp_t<T>(d) : T(0);
 #pragma unroll
     for (int i = j + 1; i < NB; ++i) {
       T t = s[i] * s[j] * m[aidx(i, j)];
@@ -212,7 +214,9 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, i
     out.y[o] = y;
     out.v[o] = v;
     out.rho[o] = (diag_all && rho > T(0)) ? rho : T(0);
-    out.ok[o] = diag_all && (rho >= tau) && (n >= no);
+    // Provisional: the caller also requires >= no samples where rho alone
+    // does not certify it.
+    out.ok[o] = diag_all && (rho >= tau);
   }
 }
 
@@ -224,18 +228,16 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, i
 // then summed in FP64.  The variance is recomputed by the caller from g.
 __device__ __forceinline__ void refine_order2(const float* m, const float* b, float* g, float& y) {
   constexpr int NB = 6;
-  float s[NB], L[NB][NB], iD[NB];
+  float s[NB], L[NB][NB], D[NB], iD[NB];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) s[i] = __frsqrt_rn(m[aidx(i, i)]);
+  for (int i = 0; i < NB; ++i) s[i] = __builtin_amdgcn_rsqf(m[aidx(i, i)]);
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     float d = s[j] * s[j] * m[aidx(j, j)];
-    float D[NB];
-#pragma unroll
-    for (int k = 0; k < j; ++k) D[k] = 1.f / iD[k];
 #pragma unroll
     for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k] * D[k];
-    iD[j] = d > 0.f ? 1.f / d : 0.f;
+    D[j] = d;
+    iD[j] = d > 0.f ? __builtin_amdgcn_rcpf(d) : 0.f;
 #pragma unroll
     for (int i = j + 1; i < NB; ++i) {
       float t = s[i] * s[j] * m[aidx(i, j)];
@@ -295,7 +297,7 @@ __device__ __forceinline__ void ici_step(IciState& st, bool ok, float y, float v
   if (!ok) return;
   st.any = true;
   if (st.stopped) return;
-  const float sd = sqrtf(fmaxf(v, 0.f));
+  const float sd = __builtin_amdgcn_sqrtf(fmaxf(v, 0.f));
   st.lo = fmaxf(st.lo, y - gamma * sd);
   st.hi = fminf(st.hi, y + gamma * sd);
   if (st.lo <= st.hi) {
@@ -396,6 +398,12 @@ __device__ __forceinline__ void stage_tile(const LaunchK& K, int u0, int v0, flo
 // terms positive) instead of the moment form g^T B g.  Above it both forms
 // carry ~1e-4 relative error or less in FP32; below it the moment form's
 // cancellation grows quickly.
+//
+// A support of fewer than n_o samples makes the normal matrix singular, whose
+// equilibrated FP32 pivot then stays within ~N u of zero; a pivot of at least
+// kPivotCertifiesN therefore certifies N >= n_o, and only fits below it have
+// their samples counted (in the same second pass).
+constexpr float kPivotCertifiesN = 1e-3f;
 
 // Visits an NB x NB box of sub-lattice points: fully unrolled, so offsets
 // advance by uniform steps and LDS reads use immediate offsets.
@@ -509,39 +517,50 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
       walk_support(K, lds, regs, Xj, Yj, c, cls, m, accumulate);
 
       Fits<float, ORDER> fr;
-      solve_fits<float, ORDER, ICI>(a.m, a.b, a.B, a.n, K.tau_inv, fr);
+      solve_fits<float, ORDER, ICI>(a.m, a.b, a.B, K.tau_inv, fr);
       if constexpr (ORDER == 2) {
         // ill-conditioned order-2 solves: FP64 iterative refinement
         if (K.use_fp64 && fr.ok[2] && fr.rho[2] < K.tau_fp64) refine_order2(a.m, a.b, fr.g[2], fr.y[2]);
       }
-      if constexpr (ICI && ORDER >= 1) {
-        // Variance of ill-conditioned fits from the samples (positive terms).
+      if constexpr (ORDER >= 1) {
+        // Second pass, taken by the whole wave when any lane needs it: count
+        // the samples of fits whose pivot does not certify N >= n_o, and
+        // recompute the variance of ill-conditioned fits from positive terms.
         bool need = false;
 #pragma unroll
-        for (int o = 1; o <= ORDER; ++o) need = need || (fr.ok[o] && fr.rho[o] < K.tau_fp64);
-        if (need) {
+        for (int o = 1; o <= ORDER; ++o)
+          need = need || (fr.ok[o] && (fr.rho[o] < kPivotCertifiesN || (ICI && fr.rho[o] < K.tau_fp64)));
+        if (__builtin_amdgcn_ballot_w64(need) != 0) {
+          int n = 0;
           float vs[ORDER + 1];
 #pragma unroll
           for (int o = 0; o <= ORDER; ++o) vs[o] = 0.f;
-          auto var_term = [&](float dx, float dy, float f, float iv) {
+          auto second = [&](float dx, float dy, float f, float iv) {
             (void)f;
             const float x2 = dx * dx, y2 = dy * dy;
             const float kw = fmaxf(__builtin_amdgcn_exp2f((x2 + y2) * kexp) - eedge, 0.f);
-            const float w2 = kw * kw * iv;
-            float phi[6] = {1.f, dx, dy, x2, dx * dy, y2};
+            n += (kw * iv > 0.f) ? 1 : 0;
+            if constexpr (ICI) {
+              const float w2 = kw * kw * iv;
+              float phi[6] = {1.f, dx, dy, x2, dx * dy, y2};
 #pragma unroll
-            for (int o = 1; o <= ORDER; ++o) {
-              constexpr int nb_tab[3] = {1, 3, 6};
-              float t = fr.g[o][0];
+              for (int o = 1; o <= ORDER; ++o) {
+                constexpr int nb_tab[3] = {1, 3, 6};
+                float t = fr.g[o][0];
 #pragma unroll
-              for (int i = 1; i < nb_tab[o]; ++i) t = __builtin_fmaf(fr.g[o][i], phi[i], t);
-              vs[o] = __builtin_fmaf(t * t, w2, vs[o]);
+                for (int i = 1; i < nb_tab[o]; ++i) t = __builtin_fmaf(fr.g[o][i], phi[i], t);
+                vs[o] = __builtin_fmaf(t * t, w2, vs[o]);
+              }
             }
           };
-          walk_support(K, lds, regs, Xj, Yj, c, cls, m, var_term);
+          walk_support(K, lds, regs, Xj, Yj, c, cls, m, second);
 #pragma unroll
-          for (int o = 1; o <= ORDER; ++o)
-            if (fr.rho[o] < K.tau_fp64) fr.v[o] = vs[o];
+          for (int o = 1; o <= ORDER; ++o) {
+            constexpr int nb_tab[3] = {1, 3, 6};
+            if (fr.rho[o] < kPivotCertifiesN && n < nb_tab[o]) fr.ok[o] = false;
+            if constexpr (ICI)
+              if (fr.rho[o] < K.tau_fp64) fr.v[o] = vs[o];
+          }
         }
       }
 #pragma unroll

@@ -104,6 +104,34 @@ def test_plain_equals_fused(torch_mod, ctx):
     assert np.array_equal(ma, mb)
 
 
+def _geometry_case(case):
+    if case == "rotzoom":
+        # strongly rotated sensors, an output grid rotated by 0.3 rad with 1.7 px
+        # spacing, a ragged 37 x 23 frame
+        sensors = R.random_rig(3, 97, 61, [1.0, 0.25, 1.0 / 16], 2.0, 8.0, 77, **configs.NOISE)
+        scene = EdgeScene(97, 61, 77, n_lines=8)
+        c, s = 1.7 * math.cos(0.3), 1.7 * math.sin(0.3)
+        params = configs.lpa_params(37, 23, 2, [1.5, 3.0], out_affine=[c, -s, 30.0, s, c, 2.0])
+        return sensors, configs.capture_all(scene, sensors, 77), params, 2
+    sensors = configs.small_rig(seed=1005, size=64)
+    scene = EdgeScene(64, 64, 1005, n_lines=6)
+    params = configs.lpa_params(256, 256, 1, [2.0, 3.0], out_affine=R.resample_output(4))
+    return sensors, configs.capture_all(scene, sensors, 1005), params, 1
+
+
+@pytest.mark.parametrize("case", ["rotzoom", "zoom4"])
+def test_unusual_geometry(torch_mod, ctx, case):
+    """Sensors rotated by up to 8 degrees under a rotated, coarser output grid
+    (ragged 37 x 23 frame), and a 4x finer output grid: full-frame parity."""
+    sensors, raws, params, order = _geometry_case(case)
+    _say(f"[gpu] geometry case={case}")
+    rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, params)
+    orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
+    st = compare(rgb, smap, orc, sensors, order, gpu_sd=LAST_SD[0])
+    _say(f"  stats {st}")
+    assert st["agree_frac"] > 0.999
+
+
 @pytest.mark.parametrize("order,radii", [(0, [2.0]), (0, [1.5, 3.0]), (1, [1.0, 2.0, 3.0, 4.0]),
                                          (2, [3.0]), (2, [1.0, 2.0, 3.0, 4.0])])
 def test_orders_and_scales(torch_mod, ctx, order, radii):
