@@ -175,6 +175,8 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output*
                         LaunchK* K) {
   const lpa_params& p = R.p;
   std::memset(K, 0, sizeof(*K));
+  if (tile_w < 2 || tile_h < 2 || (tile_w & 1) || (tile_h & 1) || tile_w * tile_h > 256)
+    return set_error(LPA_ERR_INVALID_ARG, "tile %dx%d: sides must be even, at most 256 pixels", tile_w, tile_h);
   for (int i = 0; i < 6; ++i) K->out_affine[i] = p.out_affine[i];
   K->out_w = p.out_w;
   K->out_h = p.out_h;
@@ -203,10 +205,11 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output*
       const double kappa = cls == 1 ? p.green_ratio : 1.0;
       const double r = p.radii[m] * kappa;
       const double h = R.h[m] * kappa * kappa;
-      const double cs = std::ldexp(1.0, -(int)std::ceil(std::log2(r)));
+      const double cs = std::sqrt(1.4426950408889634 / h);
       K->sc[m].radius[cls] = r;
       K->sc[m].coord_scale[cls] = (float)cs;
-      K->sc[m].k_exp[cls] = (float)(-1.4426950408889634 / (h * cs * cs));
+      const double reach = (double)(float)cs * r * (1 + 1e-4);
+      K->sc[m].reach2[cls] = (float)(reach * reach);
       K->sc[m].e_edge[cls] = (float)std::exp(-r * r / h);
     }
   }

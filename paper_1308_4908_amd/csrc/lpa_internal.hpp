@@ -45,8 +45,8 @@ struct SensorK {
 // Per-scale constants, per channel class (0: R and B, 1: G).
 struct ScaleK {
   double radius[2];   // r' = r * kappa_class
-  float coord_scale[2]; // power-of-two s with s * r' <= 1 (coordinates are scaled by s)
-  float k_exp[2];     // -log2(e) / (h' s^2): window exp2 argument per scaled |d|^2
+  float coord_scale[2]; // s = sqrt(log2(e) / h'): exp(-|d|^2 / h') = exp2(-|s d|^2)
+  float reach2[2];    // (s r' (1 + 1e-4))^2: samples at or beyond it have exactly zero weight
   float e_edge[2];    // exp(-r'^2 / h'): subtracted so the window vanishes at r'
 };
 
@@ -72,6 +72,23 @@ struct LaunchK {
   SensorK s[kMaxSensors];
   ScaleK sc[kMaxScales];
 };
+
+// Output pixel offset (du, dv) of thread tid within a tw x th tile (both even).
+// The threads are split into the four 2x2 parity classes of output pixels,
+// each laid out row-major over the tile's pixels of that parity, so a 64-lane
+// wave holds pixels two apart: their positions relative to a sensor's CFA
+// lattice differ only by the slow drift of the rig's rotation and scale, and
+// a sample outside one lane's window is then mostly outside all of them.
+#if defined(__HIPCC__)
+__host__ __device__
+#endif
+inline void lane_pixel(int tid, int tw, int th, int* du, int* dv) {
+  const int per = (tw * th) >> 2;
+  const int cls = tid / per, w = tid - cls * per;
+  const int hw = tw >> 1;
+  *du = 2 * (w % hw) + (cls & 1);
+  *dv = 2 * (w / hw) + (cls >> 1);
+}
 
 // Header of a batch table in device memory (read by the persistent kernel, so
 // a captured graph can be replayed with new table contents).

@@ -53,59 +53,64 @@ __device__ __forceinline__ void acc_zero(Acc<ORDER, ICI>& a) {
   for (int k = 0; k < (ICI ? n_mom<ORDER>() : 1); ++k) a.B[k] = 0.f;
 }
 
-// One sample: scaled offset (dx, dy), radiance f, inverse variance iv.
+// One sample: scaled offset (dx, dy), radiance f, inverse variance iv.  The
+// coordinate scale makes the Gaussian window exp2(-|d|^2); it is shifted to
+// vanish at the radius and clamped to zero beyond it.  A sample at or beyond
+// reach2 has exactly zero weight, so the update is skipped there: per lane,
+// and for the whole wave when none of its lanes has the sample in its window.
 template <int ORDER, bool ICI>
 __device__ __forceinline__ void acc_sample(Acc<ORDER, ICI>& a, float dx, float dy, float f, float iv,
-                                           float k_exp, float e_edge) {
-  float mono[n_mom<ORDER>()];
-  mono[0] = 1.f;
-  float r2;
-  if constexpr (ORDER >= 1) {
-    mono[1] = dx;
-    mono[2] = dy;
-    mono[3] = dx * dx;
-    mono[4] = dx * dy;
-    mono[5] = dy * dy;
-    r2 = mono[3] + mono[5];
-  } else {
-    r2 = __builtin_fmaf(dx, dx, dy * dy);
-  }
-  if constexpr (ORDER >= 2) {
-    mono[6] = mono[3] * dx;
-    mono[7] = mono[3] * dy;
-    mono[8] = mono[4] * dy;
-    mono[9] = mono[5] * dy;
-    mono[10] = mono[3] * mono[3];
-    mono[11] = mono[6] * dy;
-    mono[12] = mono[3] * mono[5];
-    mono[13] = mono[8] * dy;
-    mono[14] = mono[5] * mono[5];
-  }
-  // Gaussian window shifted to vanish at the radius; zero outside the disc.
-  const float kw = fmaxf(__builtin_amdgcn_exp2f(r2 * k_exp) - e_edge, 0.f);
-  const float w = kw * iv;
-  const float wf = w * f;
-  a.m[0] += w;
+                                           float e_edge, float reach2) {
+  const float x2 = dx * dx, y2 = dy * dy;
+  const float r2 = x2 + y2;
+  if (r2 < reach2) {
+    float mono[n_mom<ORDER>()];
+    mono[0] = 1.f;
+    if constexpr (ORDER >= 1) {
+      mono[1] = dx;
+      mono[2] = dy;
+      mono[3] = x2;
+      mono[4] = dx * dy;
+      mono[5] = y2;
+    }
+    if constexpr (ORDER >= 2) {
+      mono[6] = mono[3] * dx;
+      mono[7] = mono[3] * dy;
+      mono[8] = mono[4] * dy;
+      mono[9] = mono[5] * dy;
+      mono[10] = mono[3] * mono[3];
+      mono[11] = mono[6] * dy;
+      mono[12] = mono[3] * mono[5];
+      mono[13] = mono[8] * dy;
+      mono[14] = mono[5] * mono[5];
+    }
+    const float kw = fmaxf(__builtin_amdgcn_exp2f(-r2) - e_edge, 0.f);
+    const float w = kw * iv;
+    const float wf = w * f;
+    a.m[0] += w;
 #pragma unroll
-  for (int k = 1; k < n_mom<ORDER>(); ++k) a.m[k] = __builtin_fmaf(w, mono[k], a.m[k]);
-  a.b[0] += wf;
+    for (int k = 1; k < n_mom<ORDER>(); ++k) a.m[k] = __builtin_fmaf(w, mono[k], a.m[k]);
+    a.b[0] += wf;
 #pragma unroll
-  for (int k = 1; k < n_basis<ORDER>(); ++k) a.b[k] = __builtin_fmaf(wf, mono[k], a.b[k]);
-  if constexpr (ICI) {
-    const float w2 = w * kw;
-    a.B[0] += w2;
+    for (int k = 1; k < n_basis<ORDER>(); ++k) a.b[k] = __builtin_fmaf(wf, mono[k], a.b[k]);
+    if constexpr (ICI) {
+      const float w2 = w * kw;
+      a.B[0] += w2;
 #pragma unroll
-    for (int k = 1; k < n_mom<ORDER>(); ++k) a.B[k] = __builtin_fmaf(w2, mono[k], a.B[k]);
+      for (int k = 1; k < n_mom<ORDER>(); ++k) a.B[k] = __builtin_fmaf(w2, mono[k], a.B[k]);
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Register-resident solve.  LDL^T of the Jacobi-equilibrated normal matrix
-// A~ = S A S (S = diag(A)^-1/2); its leading blocks are the factorizations of
-// the order-1 and order-0 fits, so one factorization serves every order.
-// For order o: rho_o = smallest pivot among the first n_o, valid iff the
-// support has >= n_o samples and rho_o >= tau; g = A^-1 e0 = s0 S A~^-1 e0,
-// C0 = g . b and var(C0) = g^T B g.
+// Register-resident solve.  LDL^T of the normal matrix A; its leading blocks
+// are the factorizations of the order-1 and order-0 fits, so one
+// factorization serves every order.  The pivots of the Jacobi-equilibrated
+// matrix S A S (S = diag(A)^-1/2) are D_j / A_jj (the factors of S A S are
+// S L S^-1 and S D S), so the equilibration need not be formed.  For order o:
+// rho_o = smallest equilibrated pivot among the first n_o, valid iff rho_o >=
+// tau (and the support has >= n_o samples, which the caller checks where
+// rho_o does not certify it); g = A^-1 e0, C0 = g . b, var(C0) = g^T B g.
 // ---------------------------------------------------------------------------
 template <typename T, int ORDER>
 struct Fits {
@@ -117,43 +122,34 @@ struct Fits {
 };
 
 template <typename T>
-__device__ __forceinline__ T rsqrt_t(T x);
-template <typename T>
 __device__ __forceinline__ T rcp_t(T x);
 template <>
 __device__ __forceinline__ float rcp_t<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <>
 __device__ __forceinline__ double rcp_t<double>(double x) { return 1.0 / x; }
-template <>
-__device__ __forceinline__ float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-template <>
-__device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
 
 template <typename T, int ORDER, bool ICI>
 __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T tau, Fits<T, ORDER>& out) {
   constexpr int NB = n_basis<ORDER>();
-  T s[NB];
+  T L[NB][NB], U[NB][NB];  // U[i][k] = L[i][k] D[k]
+  T D[NB], iD[NB], req[NB];
   bool dok[NB];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const T aii = m[aidx(i, i)];
-    dok[i] = aii > T(0);
-    s[i] = dok[i] ? rsqrt_t<T>(aii) : T(0);
-  }
-  T L[NB][NB];
-  T D[NB], iD[NB];
-#pragma unroll
   for (int j = 0; j < NB; ++j) {
-    T d = s[j] * s[j] * m[aidx(j, j)];
+    const T ajj = m[aidx(j, j)];
+    dok[j] = ajj > T(0);
+    T d = ajj;
 #pragma unroll
-    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k] * D[k];
+    for (int k = 0; k < j; ++k) d -= U[j][k] * L[j][k];
     D[j] = d;
     iD[j] = d > T(0) ? rcp_t<T>(d) : T(0);
+    req[j] = dok[j] ? d * rcp_t<T>(ajj) : T(0);  // equilibrated pivot
 #pragma unroll
     for (int i = j + 1; i < NB; ++i) {
-      T t = s[i] * s[j] * m[aidx(i, j)];
+      T t = m[aidx(i, j)];
 #pragma unroll
-      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k] * D[k];
+      for (int k = 0; k < j; ++k) t -= U[i][k] * L[j][k];
+      U[i][j] = t;
       L[i][j] = t * iD[j];
     }
   }
@@ -175,23 +171,22 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T
     const int no = nb_tab[o];
 #pragma unroll
     for (int i = (o == 0 ? 0 : nb_tab[o - 1]); i < no; ++i) {
-      rho = D[i] < rho ? D[i] : rho;
+      rho = req[i] < rho ? req[i] : rho;
       diag_all = diag_all && dok[i];
     }
-    T x[NB];
+    T g[NB];
 #pragma unroll
     for (int i = NB - 1; i >= 0; --i) {
       if (i < no) {
         T t = z[i] * iD[i];
 #pragma unroll
         for (int k = i + 1; k < NB; ++k)
-          if (k < no) t -= L[k][i] * x[k];
-        x[i] = t;
+          if (k < no) t -= L[k][i] * g[k];
+        g[i] = t;
+      } else {
+        g[i] = T(0);
       }
     }
-    T g[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) g[i] = (i < no) ? s[0] * s[i] * x[i] : T(0);
 #pragma unroll
     for (int i = 0; i < NB; ++i) out.g[o][i] = g[i];
     T y = T(0);
@@ -405,43 +400,41 @@ __device__ __forceinline__ void stage_tile(const LaunchK& K, int u0, int v0, flo
 // their samples counted (in the same second pass).
 constexpr float kPivotCertifiesN = 1e-3f;
 
-// Visits an NB x NB box of sub-lattice points: fully unrolled, so offsets
-// advance by uniform steps and LDS reads use immediate offsets.
-template <int NB, class Fn>
-__device__ __forceinline__ void walk_box_fixed(const float2* p0, int row_step, float c0x, float c0y,
-                                               float sax, float say, float sbx, float sby, Fn& fn) {
-  float rx = c0x, ry = c0y;
-#pragma unroll
-  for (int jj = 0; jj < NB; ++jj) {
-    const float2* prow = p0 + jj * row_step;
-    float dx = rx, dy = ry;
-#pragma unroll
-    for (int ii = 0; ii < NB; ++ii) {
-      const float2 sm = prow[2 * ii];
-      fn(dx, dy, sm.x, sm.y);
-      dx += sax;
-      dy += say;
-    }
-    rx += sbx;
-    ry += sby;
-  }
-}
+// Visits an nx x ny box of sub-lattice points in blocks of kBlk x kBlk: the
+// block body is unrolled behind uniform guards, so offsets advance by uniform
+// steps, LDS reads use immediate offsets, and every box size runs the same
+// code (separately inlined walks per size would make the compiler copy each
+// accumulator where they merge).
+constexpr int kBlk = 5;
 
 template <class Fn>
-__device__ __forceinline__ void walk_box_any(const float2* p0, int row_step, int nx, int ny, float c0x, float c0y,
-                                             float sax, float say, float sbx, float sby, Fn& fn) {
-  float rx = c0x, ry = c0y;
-  for (int jj = 0; jj < ny; ++jj) {
-    const float2* prow = p0 + jj * row_step;
-    float dx = rx, dy = ry;
-    for (int ii = 0; ii < nx; ++ii) {
-      const float2 sm = prow[2 * ii];
-      fn(dx, dy, sm.x, sm.y);
-      dx += sax;
-      dy += say;
+__device__ __forceinline__ void walk_box(const float2* p0, int row_step, int nx, int ny, float c0x, float c0y,
+                                         float sax, float say, float sbx, float sby, Fn& fn) {
+  for (int jb = 0; jb < ny; jb += kBlk) {
+    for (int ib = 0; ib < nx; ib += kBlk) {
+      const int mx = nx - ib, my = ny - jb;
+      const float2* pb = p0 + jb * row_step + 2 * ib;
+      float rx = __builtin_fmaf((float)ib, sax, __builtin_fmaf((float)jb, sbx, c0x));
+      float ry = __builtin_fmaf((float)ib, say, __builtin_fmaf((float)jb, sby, c0y));
+#pragma unroll
+      for (int jj = 0; jj < kBlk; ++jj) {
+        if (jj < my) {
+          const float2* prow = pb + jj * row_step;
+          float dx = rx, dy = ry;
+#pragma unroll
+          for (int ii = 0; ii < kBlk; ++ii) {
+            if (ii < mx) {
+              const float2 sm = prow[2 * ii];
+              fn(dx, dy, sm.x, sm.y);
+              dx += sax;
+              dy += say;
+            }
+          }
+          rx += sbx;
+          ry += sby;
+        }
+      }
     }
-    rx += sbx;
-    ry += sby;
   }
 }
 
@@ -464,8 +457,8 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
     const int nx = S.nbox[cls][m][0];
     const int ny = S.nbox[cls][m][1];
     // step between sub-lattice points (+2 px in x or y), scaled
-    const float sax = (float)(2.0 * S.fwd[0]) * cs, say = (float)(2.0 * S.fwd[3]) * cs;
-    const float sbx = (float)(2.0 * S.fwd[1]) * cs, sby = (float)(2.0 * S.fwd[4]) * cs;
+    const float sax = (float)(2.0 * S.fwd[0] * cs), say = (float)(2.0 * S.fwd[3] * cs);
+    const float sbx = (float)(2.0 * S.fwd[1] * cs), sby = (float)(2.0 * S.fwd[4] * cs);
     const float2* plane = lds + S.lds_off;
     const int row_step = 2 * R.w;
     const int nsub = S.sub_n[c];
@@ -480,14 +473,7 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
       const float c0x = (float)((Xb - Xj) * cs);
       const float c0y = (float)((Yb - Yj) * cs);
       const float2* p0 = plane + (yb - R.y0) * R.w + (xb - R.x0);
-      switch (nx == ny ? nx : 0) {
-        case 1: walk_box_fixed<1>(p0, row_step, c0x, c0y, sax, say, sbx, sby, fn); break;
-        case 2: walk_box_fixed<2>(p0, row_step, c0x, c0y, sax, say, sbx, sby, fn); break;
-        case 3: walk_box_fixed<3>(p0, row_step, c0x, c0y, sax, say, sbx, sby, fn); break;
-        case 4: walk_box_fixed<4>(p0, row_step, c0x, c0y, sax, say, sbx, sby, fn); break;
-        case 5: walk_box_fixed<5>(p0, row_step, c0x, c0y, sax, say, sbx, sby, fn); break;
-        default: walk_box_any(p0, row_step, nx, ny, c0x, c0y, sax, say, sbx, sby, fn); break;
-      }
+      walk_box(p0, row_step, nx, ny, c0x, c0y, sax, say, sbx, sby, fn);
     }
   }
 }
@@ -507,12 +493,12 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
     for (int o = 0; o <= ORDER; ++o) ici_init(st[o]);
 
     for (int m = 0; m < K.n_scales; ++m) {
-      const float kexp = K.sc[m].k_exp[cls];
       const float eedge = K.sc[m].e_edge[cls];
+      const float reach2 = K.sc[m].reach2[cls];
       Acc<ORDER, ICI> a;
       acc_zero(a);
       auto accumulate = [&](float dx, float dy, float f, float iv) {
-        acc_sample<ORDER, ICI>(a, dx, dy, f, iv, kexp, eedge);
+        acc_sample<ORDER, ICI>(a, dx, dy, f, iv, eedge, reach2);
       };
       walk_support(K, lds, regs, Xj, Yj, c, cls, m, accumulate);
 
@@ -538,18 +524,21 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
           auto second = [&](float dx, float dy, float f, float iv) {
             (void)f;
             const float x2 = dx * dx, y2 = dy * dy;
-            const float kw = fmaxf(__builtin_amdgcn_exp2f((x2 + y2) * kexp) - eedge, 0.f);
-            n += (kw * iv > 0.f) ? 1 : 0;
-            if constexpr (ICI) {
-              const float w2 = kw * kw * iv;
-              float phi[6] = {1.f, dx, dy, x2, dx * dy, y2};
+            const float r2 = x2 + y2;
+            if (r2 < reach2) {
+              const float kw = fmaxf(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f);
+              n += (kw * iv > 0.f) ? 1 : 0;
+              if constexpr (ICI) {
+                const float w2 = kw * kw * iv;
+                float phi[6] = {1.f, dx, dy, x2, dx * dy, y2};
 #pragma unroll
-              for (int o = 1; o <= ORDER; ++o) {
-                constexpr int nb_tab[3] = {1, 3, 6};
-                float t = fr.g[o][0];
+                for (int o = 1; o <= ORDER; ++o) {
+                  constexpr int nb_tab[3] = {1, 3, 6};
+                  float t = fr.g[o][0];
 #pragma unroll
-                for (int i = 1; i < nb_tab[o]; ++i) t = __builtin_fmaf(fr.g[o][i], phi[i], t);
-                vs[o] = __builtin_fmaf(t * t, w2, vs[o]);
+                  for (int i = 1; i < nb_tab[o]; ++i) t = __builtin_fmaf(fr.g[o][i], phi[i], t);
+                  vs[o] = __builtin_fmaf(t * t, w2, vs[o]);
+                }
               }
             }
           };
@@ -611,10 +600,12 @@ __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2*
   const int nthreads = K.tile_w * K.tile_h;
   stage_tile<SRC>(K, u0, v0, lds, regs, tid, nthreads);
   __syncthreads();
-  const int u = u0 + tid % K.tile_w;
-  const int v = v0 + tid / K.tile_w;
+  int du, dv;
+  lane_pixel(tid, K.tile_w, K.tile_h, &du, &dv);
+  const int u = u0 + du, v = v0 + dv;
   const bool active = (u < K.out_w) && (v < K.out_h);
-  fit_pixel<ORDER, ICI>(K, lds, regs, active ? u : u0, active ? v : v0, active);
+  // inactive lanes of a ragged tile compute at their nominal pixel (staged)
+  fit_pixel<ORDER, ICI>(K, lds, regs, u, v, active);
 }
 
 template <int ORDER, bool ICI, int SRC>

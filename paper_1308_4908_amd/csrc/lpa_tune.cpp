@@ -154,7 +154,8 @@ lpa_status lpa_tuner_load(lpa_ctx* ctx, const char* path) {
                     "\"zoom_q\": %d, \"tile_w\": %d, \"tile_h\": %d, \"occupancy\": %d}",
                     &k.order, &k.n_scales, &k.n_sensors, &k.src_kind, &k.radius_q, &k.zoom_q, &c.tile_w,
                     &c.tile_h, &c.occupancy) == 9) {
-      const bool ok_tile = c.tile_w > 0 && c.tile_h > 0 && c.tile_w * c.tile_h == 256;
+      const bool ok_tile = c.tile_w > 0 && c.tile_h > 0 && c.tile_w % 2 == 0 && c.tile_h % 2 == 0 &&
+                           c.tile_w * c.tile_h == 256;
       if (!ok_tile || (c.occupancy != 0 && c.occupancy != 4)) {
         std::fclose(f);
         return set_error(LPA_ERR_INVALID_ARG, "bad tuner entry in %s", path);
