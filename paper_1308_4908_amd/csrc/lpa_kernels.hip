@@ -608,21 +608,33 @@ __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2*
   fit_pixel<ORDER, ICI>(K, lds, regs, u, v, active);
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i runs on
+// XCD i mod 8), each with its own L2.  Giving XCD x a contiguous range of
+// tiles keeps the halo a tile shares with its neighbours in that XCD's L2
+// instead of fetching it from HBM once per XCD.  A bijection on [0, n).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int i, int n) {
+  const int q = n / kXcds, r = n - q * kXcds;
+  const int x = i % kXcds, j = i / kXcds;
+  return x * q + (x < r ? x : r) + j;
+}
+
 template <int ORDER, bool ICI, int SRC>
 __global__ void __launch_bounds__(256) fit_kernel(const LaunchK K) {
   extern __shared__ float2 lds[];
   __shared__ Region regs[kMaxSensors];
-  process_tile<ORDER, ICI, SRC>(K, blockIdx.x, lds, regs);
+  process_tile<ORDER, ICI, SRC>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
 }
 
-// Same kernel compiled for 4 waves per SIMD (<= 128 VGPRs, a few spills in
-// cold paths); the tuner picks whichever is faster for a frame's class.
+// Same kernel compiled for 4 waves per SIMD (<= 128 VGPRs: some values spill
+// to scratch around each window walk, outside the per-sample loop); the tuner
+// picks whichever is faster for a frame's class.
 template <int ORDER, bool ICI, int SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 fit_kernel_occ4(const LaunchK K) {
   extern __shared__ float2 lds[];
   __shared__ Region regs[kMaxSensors];
-  process_tile<ORDER, ICI, SRC>(K, blockIdx.x, lds, regs);
+  process_tile<ORDER, ICI, SRC>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
 }
 
 // Persistent form: workgroups take tiles from a device counter until the
