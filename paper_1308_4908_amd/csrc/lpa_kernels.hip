@@ -483,9 +483,6 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
                                           int u, int v, bool active) {
   const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
   const double Yj = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
-  float rgb[3], sdv[3];
-  uint8_t code[3];
-
   for (int c = 0; c < 3; ++c) {
     const int cls = (c == 1) ? 1 : 0;
     IciState st[ORDER + 1];
@@ -566,27 +563,16 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
         cd = (uint8_t)((o << 4) | st[o].chosen);
       }
     }
-    rgb[c] = val;
-    sdv[c] = sdc;
-    code[c] = cd;
-  }
-
-  if (active) {
-    float* orow = reinterpret_cast<float*>(reinterpret_cast<char*>(K.rgb) + (int64_t)v * K.rgb_pitch);
-    orow[3 * u + 0] = rgb[0];
-    orow[3 * u + 1] = rgb[1];
-    orow[3 * u + 2] = rgb[2];
-    if (K.map) {
-      uint8_t* mrow = K.map + (int64_t)v * K.map_pitch;
-      mrow[3 * u + 0] = code[0];
-      mrow[3 * u + 1] = code[1];
-      mrow[3 * u + 2] = code[2];
-    }
-    if (K.sd) {
-      float* srow = reinterpret_cast<float*>(reinterpret_cast<char*>(K.sd) + (int64_t)v * K.sd_pitch);
-      srow[3 * u + 0] = sdv[0];
-      srow[3 * u + 1] = sdv[1];
-      srow[3 * u + 2] = sdv[2];
+    // written as soon as the channel is done: nothing of it stays live
+    // through the next channel's walks
+    if (active) {
+      float* orow = reinterpret_cast<float*>(reinterpret_cast<char*>(K.rgb) + (int64_t)v * K.rgb_pitch);
+      orow[3 * u + c] = val;
+      if (K.map) K.map[(int64_t)v * K.map_pitch + 3 * u + c] = cd;
+      if (K.sd) {
+        float* srow = reinterpret_cast<float*>(reinterpret_cast<char*>(K.sd) + (int64_t)v * K.sd_pitch);
+        srow[3 * u + c] = sdc;
+      }
     }
   }
 }
