@@ -129,7 +129,8 @@ template <>
 __device__ __forceinline__ double rcp_t<double>(double x) { return 1.0 / x; }
 
 template <typename T, int ORDER, bool ICI>
-__device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T tau, Fits<T, ORDER>& out) {
+__device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T tau, bool lower,
+                                           Fits<T, ORDER>& out) {
   constexpr int NB = n_basis<ORDER>();
   T L[NB][NB], U[NB][NB];  // U[i][k] = L[i][k] D[k]
   T D[NB], iD[NB], req[NB];
@@ -173,6 +174,13 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T
     for (int i = (o == 0 ? 0 : nb_tab[o - 1]); i < no; ++i) {
       rho = req[i] < rho ? req[i] : rho;
       diag_all = diag_all && dok[i];
+    }
+    if (o < ORDER && !lower) {  // lower orders not needed (wave-uniform)
+      out.y[o] = out.v[o] = out.rho[o] = T(0);
+      out.ok[o] = false;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) out.g[o][i] = T(0);
+      continue;
     }
     T g[NB];
 #pragma unroll
@@ -499,8 +507,12 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
       };
       walk_support(K, lds, regs, Xj, Yj, c, cls, m, accumulate);
 
+      // Once every lane of the wave has a valid top-order fit at some radius,
+      // the output is that order's ICI result: the lower orders (kept only
+      // for fallback) are no longer solved.
+      const bool lower = __builtin_amdgcn_ballot_w64(!st[ORDER].any) != 0;
       Fits<float, ORDER> fr;
-      solve_fits<float, ORDER, ICI>(a.m, a.b, a.B, K.tau_inv, fr);
+      solve_fits<float, ORDER, ICI>(a.m, a.b, a.B, K.tau_inv, lower, fr);
       if constexpr (ORDER == 2) {
         // ill-conditioned order-2 solves: FP64 iterative refinement
         if (K.use_fp64 && fr.ok[2] && fr.rho[2] < K.tau_fp64) refine_order2(a.m, a.b, fr.g[2], fr.y[2]);
@@ -550,7 +562,8 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
         }
       }
 #pragma unroll
-      for (int o = 0; o <= ORDER; ++o) ici_step(st[o], fr.ok[o], fr.y[o], fr.v[o], K.gamma, m);
+      for (int o = 0; o <= ORDER; ++o)
+        if (o == ORDER || lower) ici_step(st[o], fr.ok[o], fr.y[o], fr.v[o], K.gamma, m);
     }
 
     float val = __builtin_nanf(""), sdc = __builtin_nanf("");
