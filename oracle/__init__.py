@@ -75,6 +75,25 @@ class _Fit(ctypes.Structure):
     ]
 
 
+class _Adapt(ctypes.Structure):
+    _fields_ = [
+        ("alpha", ctypes.c_double),
+        ("lambda1", ctypes.c_double),
+        ("lambda2", ctypes.c_double),
+        ("grad_radius", ctypes.c_double),
+        ("grad_h", ctypes.c_double),
+        ("max_stretch", ctypes.c_double),
+        ("grad_order", ctypes.c_int32),
+        ("grad_halfwin", ctypes.c_int32),
+    ]
+
+
+# Adaptive (CALPA) parameters: the paper's regularisers (Sec. 5.4) and the
+# readings R20..R22 (analysis window, stretch bound, gradient fit).
+ADAPT_DEFAULTS = {"alpha": 0.005, "lambda1": 1.0, "lambda2": 0.001, "grad_radius": 2.0, "grad_h": 0.0,
+                  "max_stretch": 2.0, "grad_order": 1, "grad_halfwin": 2}
+
+
 FIT_DTYPE = np.dtype(
     [("yhat", "f8"), ("var", "f8"), ("rho", "f8"), ("c1x", "f8"), ("c1y", "f8"), ("l1f", "f8"),
      ("sens_y", "f8"), ("sens_v", "f8"),
@@ -111,6 +130,23 @@ def _load():
             ctypes.POINTER(_Sensor), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
             ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ]
+        lib.orc_reconstruct_steered.restype = ctypes.c_int
+        lib.orc_reconstruct_steered.argtypes = [
+            ctypes.POINTER(_Sensor), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+            ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ]
+        lib.orc_gradients.restype = ctypes.c_int
+        lib.orc_gradients.argtypes = [
+            ctypes.POINTER(_Sensor), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+            ctypes.POINTER(_Params), ctypes.POINTER(_Adapt), ctypes.c_void_p, ctypes.c_int64,
+            ctypes.c_void_p, ctypes.c_void_p,
+        ]
+        lib.orc_steering.restype = ctypes.c_int
+        lib.orc_steering.argtypes = [
+            ctypes.POINTER(_Params), ctypes.POINTER(_Adapt), ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
         ]
         lib.orc_sample_radiance.restype = ctypes.c_int
         lib.orc_sample_radiance.argtypes = [
@@ -234,3 +270,127 @@ def ici_select(yhat, var, valid, gamma: float = 2.0):
     k = lib.orc_ici_select(len(y), y.ctypes.data, v.ctypes.data, ok.ctypes.data, float(gamma),
                            ctypes.byref(mu), ctypes.byref(gp))
     return k, mu.value, gp.value
+
+
+def _adapt_struct(a: dict | None) -> _Adapt:
+    d = dict(ADAPT_DEFAULTS, **(a or {}))
+    q = _Adapt()
+    for k in ("alpha", "lambda1", "lambda2", "grad_radius", "grad_h", "max_stretch"):
+        setattr(q, k, float(d[k]))
+    q.grad_order = int(d["grad_order"])
+    q.grad_halfwin = int(d["grad_halfwin"])
+    return q
+
+
+def _pixels(params, pixels):
+    if pixels is None:
+        return None, int(params["out_w"]) * int(params["out_h"])
+    pix = np.ascontiguousarray(np.asarray(pixels, dtype=np.int32).reshape(-1, 2))
+    return pix, pix.shape[0]
+
+
+def gradients(sensors, raws, params, adapt=None, pixels=None, exhaustive=False):
+    """Stage 1 of CALPA (Sec. 5.4, 5.5): G-channel gradients of an isotropic
+    fit at the listed pixels (default: the whole grid).  Returns (grad (n, 2),
+    valid (n,)); invalid fits give a zero gradient."""
+    lib = _load()
+    ns = len(sensors)
+    sens = (_Sensor * ns)(*[_sensor_struct(d) for d in sensors])
+    planes = [np.ascontiguousarray(np.asarray(r), dtype=np.float64) for r in raws]
+    ptrs = (ctypes.c_void_p * ns)(*[pl.ctypes.data for pl in planes])
+    prm = _params_struct(params, exhaustive)
+    ad = _adapt_struct(adapt)
+    pix, n = _pixels(params, pixels)
+    grad = np.zeros((n, 2), np.float64)
+    valid = np.zeros(n, np.int32)
+    rc = lib.orc_gradients(sens, ns, ptrs, ctypes.byref(prm), ctypes.byref(ad),
+                           pix.ctypes.data if pix is not None else None, n, grad.ctypes.data, valid.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle rejected its arguments (code {rc})")
+    return grad, valid
+
+
+def steering(params, adapt, grad_plane, pixels=None, want_diag=False):
+    """Stage 2 of CALPA (Sec. 5.4): steering matrices (n, 3) = (cxx, cxy, cyy)
+    from a gradient plane of shape (out_h, out_w, 2); optionally the
+    diagnostics (n, 5) = (s1, s2, theta, sigma, gamma)."""
+    lib = _load()
+    prm = _params_struct(params, False)
+    ad = _adapt_struct(adapt)
+    g = np.ascontiguousarray(np.asarray(grad_plane, np.float64))
+    if g.shape != (int(params["out_h"]), int(params["out_w"]), 2):
+        raise ValueError(f"gradient plane shape {g.shape} does not match the output grid")
+    pix, n = _pixels(params, pixels)
+    C = np.zeros((n, 3), np.float64)
+    diag = np.zeros((n, 5), np.float64) if want_diag else None
+    rc = lib.orc_steering(ctypes.byref(prm), ctypes.byref(ad), g.ctypes.data,
+                          pix.ctypes.data if pix is not None else None, n, C.ctypes.data,
+                          diag.ctypes.data if diag is not None else None)
+    if rc != 0:
+        raise ValueError(f"oracle rejected its arguments (code {rc})")
+    return (C, diag) if want_diag else C
+
+
+def reconstruct_steered(sensors, raws, params, C, pixels=None, want_fits=False, exhaustive=False):
+    """Stage 3 of CALPA: LPA-ICI with the window exp(-d'Cd/h) (C: (n, 3) per
+    listed pixel).  Returns the same dict as reconstruct()."""
+    lib = _load()
+    ns = len(sensors)
+    sens = (_Sensor * ns)(*[_sensor_struct(d) for d in sensors])
+    planes = [np.ascontiguousarray(np.asarray(r), dtype=np.float64) for r in raws]
+    ptrs = (ctypes.c_void_p * ns)(*[pl.ctypes.data for pl in planes])
+    prm = _params_struct(params, exhaustive)
+    pix, n = _pixels(params, pixels)
+    Cm = np.ascontiguousarray(np.asarray(C, np.float64).reshape(n, 3))
+    rgb = np.empty((n, 3), np.float64)
+    smap = np.empty((n, 3), np.uint8)
+    margin = np.empty((n, 3), np.float64)
+    gap = np.empty((n, 3), np.float64)
+    fits = np.zeros((n, 3, prm.n_scales, 3), FIT_DTYPE) if want_fits else None
+    rc = lib.orc_reconstruct_steered(
+        sens, ns, ptrs, ctypes.byref(prm), Cm.ctypes.data, pix.ctypes.data if pix is not None else None, n,
+        rgb.ctypes.data, smap.ctypes.data, margin.ctypes.data, gap.ctypes.data,
+        fits.ctypes.data if fits is not None else None,
+    )
+    if rc != 0:
+        raise ValueError(f"oracle rejected its arguments (code {rc})")
+    out = {"rgb": rgb, "scale_map": smap, "margin": margin, "gap": gap}
+    if fits is not None:
+        out["fits"] = fits
+    return out
+
+
+def neighbourhood(params, adapt, pixels):
+    """Output pixels whose gradients the steering of the listed pixels reads."""
+    q = int(dict(ADAPT_DEFAULTS, **(adapt or {}))["grad_halfwin"])
+    W, H = int(params["out_w"]), int(params["out_h"])
+    pix = np.asarray(pixels, np.int64).reshape(-1, 2)
+    need = np.zeros((H, W), bool)
+    for b in range(-q, q + 1):
+        for a in range(-q, q + 1):
+            u = np.clip(pix[:, 0] + a, 0, W - 1)
+            v = np.clip(pix[:, 1] + b, 0, H - 1)
+            need[v, u] = True
+    v, u = np.nonzero(need)
+    return np.stack([u, v], 1).astype(np.int32)
+
+
+def reconstruct_adaptive(sensors, raws, params, adapt=None, pixels=None, want_fits=False, want_stages=False):
+    """CALPA end to end (Sec. 5.4, 5.5): gradients at every pixel the listed
+    pixels' analysis windows read, steering matrices, steered reconstruction."""
+    W, H = int(params["out_w"]), int(params["out_h"])
+    if pixels is None:
+        v, u = np.mgrid[0:H, 0:W]
+        pix = np.stack([u.ravel(), v.ravel()], 1).astype(np.int32)
+    else:
+        pix = np.asarray(pixels, np.int32).reshape(-1, 2)
+    need = neighbourhood(params, adapt, pix)
+    g, _ = gradients(sensors, raws, params, adapt, pixels=need)
+    plane = np.zeros((H, W, 2), np.float64)
+    plane[need[:, 1], need[:, 0]] = g
+    C = steering(params, adapt, plane, pixels=pix)
+    out = reconstruct_steered(sensors, raws, params, C, pixels=pix, want_fits=want_fits)
+    if want_stages:
+        out["grad_plane"] = plane
+        out["C"] = C
+    return out

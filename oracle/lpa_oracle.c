@@ -109,12 +109,22 @@ static void affine_apply(const double a[6], double x, double y, double* X, doubl
 }
 
 /* Support set of output position (X, Y) for channel c and radius r with
- * window parameter h (Sec. 5.2 supp W_H; Sec. 4.2 X = T_s(x); R2, R4, R5). */
+ * window parameter h (Sec. 5.2 supp W_H; Sec. 4.2 X = T_s(x); R2, R4, R5).
+ * With a steering matrix C (3 entries, Sec. 5.4, R18) the window is
+ * exp(-d'Cd / h) - exp(-r^2 / h) on the ellipse d'Cd < r^2; C == NULL is
+ * the isotropic window (C = I). */
 static int gather_support(const orc_sensor* sensors, int n_sensors, const double* const* raw,
-                          double X, double Y, int c, double r, double h, int exhaustive,
-                          sample_list* out) {
+                          double X, double Y, int c, double r, double h, const double* C,
+                          int exhaustive, sample_list* out) {
   out->n = 0;
   const double k_edge = exp(-r * r / h);
+  /* the ellipse lies inside the disc of radius r / sqrt(smallest eigenvalue of C) */
+  double reff = r;
+  if (C) {
+    const double lmin = 0.5 * (C[0] + C[2]) - sqrt(0.25 * (C[0] - C[2]) * (C[0] - C[2]) + C[1] * C[1]);
+    if (!(lmin > 0.0)) return -1;
+    reff = r / sqrt(lmin);
+  }
   for (int s = 0; s < n_sensors; ++s) {
     const orc_sensor* S = &sensors[s];
     const double* a = S->affine;
@@ -125,7 +135,7 @@ static int gather_support(const orc_sensor* sensors, int n_sensors, const double
       const double i00 = a[4] / det, i01 = -a[1] / det, i10 = -a[3] / det, i11 = a[0] / det;
       const double px = i00 * (X - a[2]) + i01 * (Y - a[5]);
       const double py = i10 * (X - a[2]) + i11 * (Y - a[5]);
-      const double wx = r * sqrt(i00 * i00 + i01 * i01), wy = r * sqrt(i10 * i10 + i11 * i11);
+      const double wx = reff * sqrt(i00 * i00 + i01 * i01), wy = reff * sqrt(i10 * i10 + i11 * i11);
       const double bx0 = floor(px - wx) - 1, bx1 = ceil(px + wx) + 1;
       const double by0 = floor(py - wy) - 1, by1 = ceil(py + wy) + 1;
       if (bx1 < 0 || by1 < 0 || bx0 > S->width - 1 || by0 > S->height - 1) continue;
@@ -142,7 +152,7 @@ static int gather_support(const orc_sensor* sensors, int n_sensors, const double
         double Xk, Yk;
         affine_apply(a, (double)x, (double)y, &Xk, &Yk);
         const double dx = Xk - X, dy = Yk - Y;
-        const double d2 = dx * dx + dy * dy;
+        const double d2 = C ? C[0] * dx * dx + 2.0 * C[1] * dx * dy + C[2] * dy * dy : dx * dx + dy * dy;
         if (!(d2 < r * r)) continue;
         const double k = exp(-d2 / h) - k_edge;
         if (!(k > 0.0)) continue;
@@ -251,7 +261,7 @@ static void fit_order(const sample_list* S, int n, double tau_inv, orc_fit* out)
   if (!(rho > 0.0)) return;
 
   /* C = D^-1/2 At^-1 D^-1/2 b and g = A^-1 e0 with D = diag(A). */
-  double rhs[NB_MAX], u[NB_MAX], C[NB_MAX], g[NB_MAX];
+  double rhs[NB_MAX] = {0}, u[NB_MAX], C[NB_MAX], g[NB_MAX];
   for (int i = 0; i < n; ++i) rhs[i] = scale[i] * b[i];
   chol_solve(n, L, rhs, u);
   for (int i = 0; i < n; ++i) C[i] = scale[i] * u[i];
@@ -307,10 +317,9 @@ static void fit_order(const sample_list* S, int n, double tau_inv, orc_fit* out)
   out->valid = (S->n >= n) && (rho >= tau_inv);
 }
 
-int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
-                    const orc_params* P, const int32_t* pixels, int64_t n_pixels, double* rgb,
-                    uint8_t* scale_map, double* margin, double* gap, orc_fit* fits) {
-  if (!sensors || !raw || !P || !rgb) return -1;
+static int check_args(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
+                      const orc_params* P, const int32_t* pixels, int64_t n_pixels) {
+  if (!sensors || !raw || !P) return -1;
   if (n_sensors < 1 || n_sensors > ORC_MAX_SENSORS) return -2;
   if (P->order < 0 || P->order > 2) return -3;
   if (P->n_scales < 1 || P->n_scales > ORC_MAX_SCALES) return -4;
@@ -322,6 +331,34 @@ int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* 
         !(S->read_sigma > 0) || det == 0.0 || S->cfa < 0 || S->cfa > 3 || !raw[s])
       return -6;
   }
+  return 0;
+}
+
+static int reconstruct_impl(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
+                            const orc_params* P, const double* Cpix, const int32_t* pixels,
+                            int64_t n_pixels, double* rgb, uint8_t* scale_map, double* margin,
+                            double* gap, orc_fit* fits);
+
+int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
+                    const orc_params* P, const int32_t* pixels, int64_t n_pixels, double* rgb,
+                    uint8_t* scale_map, double* margin, double* gap, orc_fit* fits) {
+  return reconstruct_impl(sensors, n_sensors, raw, P, NULL, pixels, n_pixels, rgb, scale_map, margin, gap, fits);
+}
+
+int orc_reconstruct_steered(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
+                            const orc_params* P, const double* C, const int32_t* pixels,
+                            int64_t n_pixels, double* rgb, uint8_t* scale_map, double* margin,
+                            double* gap, orc_fit* fits) {
+  return reconstruct_impl(sensors, n_sensors, raw, P, C, pixels, n_pixels, rgb, scale_map, margin, gap, fits);
+}
+
+static int reconstruct_impl(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
+                            const orc_params* P, const double* Cpix, const int32_t* pixels,
+                            int64_t n_pixels, double* rgb, uint8_t* scale_map, double* margin,
+                            double* gap, orc_fit* fits) {
+  const int rc = check_args(sensors, n_sensors, raw, P, pixels, n_pixels);
+  if (rc) return rc;
+  if (!rgb) return -1;
   const int M = P->order;
   const int nS = P->n_scales;
   static const int basis_size[3] = {1, 3, 6};
@@ -340,7 +377,8 @@ int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* 
         const double r = P->radii[m] * kappa;
         const double h0 = P->h[m] > 0.0 ? P->h[m] : 2.0 * P->radii[m] * P->radii[m] / 9.0;
         const double h = h0 * kappa * kappa;
-        if (gather_support(sensors, n_sensors, raw, X, Y, c, r, h, P->exhaustive, &list)) {
+        if (gather_support(sensors, n_sensors, raw, X, Y, c, r, h, Cpix ? Cpix + 3 * p : NULL, P->exhaustive,
+                           &list)) {
           free(list.v);
           return -7;
         }
@@ -377,5 +415,105 @@ int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* 
     }
   }
   free(list.v);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * CALPA stages (Sec. 5.4, Sec. 5.5; readings R18..R22 in lpa_oracle.h).
+ * ------------------------------------------------------------------------- */
+
+/* Stage 1: the gradient (C1) of an isotropic fit of the G channel, Sec. 5.4
+ * first step with the G channel of Sec. 5.5 (R22). */
+int orc_gradients(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
+                  const orc_params* P, const orc_adapt* A, const int32_t* pixels, int64_t n_pixels,
+                  double* grad, int32_t* valid) {
+  const int rc = check_args(sensors, n_sensors, raw, P, pixels, n_pixels);
+  if (rc) return rc;
+  if (!A || !grad || A->grad_order < 1 || A->grad_order > 2 || !(A->grad_radius > 0)) return -8;
+  static const int basis_size[3] = {1, 3, 6};
+  const double kappa = P->green_ratio;
+  const double r = A->grad_radius * kappa;
+  const double h0 = A->grad_h > 0.0 ? A->grad_h : 2.0 * A->grad_radius * A->grad_radius / 9.0;
+  const double h = h0 * kappa * kappa;
+  sample_list list = {0, 0, 0};
+  for (int64_t p = 0; p < n_pixels; ++p) {
+    const int32_t u = pixels ? pixels[2 * p] : (int32_t)(p % P->out_w);
+    const int32_t v = pixels ? pixels[2 * p + 1] : (int32_t)(p / P->out_w);
+    double X, Y;
+    affine_apply(P->out_affine, (double)u, (double)v, &X, &Y);
+    if (gather_support(sensors, n_sensors, raw, X, Y, 1, r, h, NULL, P->exhaustive, &list)) {
+      free(list.v);
+      return -7;
+    }
+    orc_fit fit;
+    fit_order(&list, basis_size[A->grad_order], P->tau_inv, &fit);
+    grad[2 * p] = fit.valid ? fit.c1x : 0.0;
+    grad[2 * p + 1] = fit.valid ? fit.c1y : 0.0;
+    if (valid) valid[p] = fit.valid;
+  }
+  free(list.v);
+  return 0;
+}
+
+/* Stage 2: steering matrix of Sec. 5.4 from the gradients of the (2q+1)^2
+ * output pixels around j (R20).  The singular values of the stacked gradient
+ * matrix G are the square roots of the eigenvalues of G^T G; its second right
+ * singular vector v is the direction of least gradient energy (along the
+ * edge) and gives theta = arctan(v1 / v2).  With U_theta as printed, whose
+ * second column is parallel to v, C = gamma U diag(sigma, 1/sigma) U^T
+ * (R19) has eigenvalue gamma*sigma across the edge and gamma/sigma along it;
+ * both are clamped (R21). */
+int orc_steering(const orc_params* P, const orc_adapt* A, const double* grad_plane,
+                 const int32_t* pixels, int64_t n_pixels, double* C, double* diag) {
+  if (!P || !A || !grad_plane || !C) return -1;
+  if (!pixels && n_pixels != (int64_t)P->out_w * P->out_h) return -5;
+  if (A->grad_halfwin < 0 || !(A->max_stretch >= 1.0) || !(A->alpha >= 0.0) || !(A->lambda1 >= 0.0) ||
+      !(A->lambda2 >= 0.0))
+    return -8;
+  const int q = A->grad_halfwin;
+  const double lo = 1.0 / (A->max_stretch * A->max_stretch), hi = A->max_stretch * A->max_stretch;
+  for (int64_t p = 0; p < n_pixels; ++p) {
+    const int32_t u = pixels ? pixels[2 * p] : (int32_t)(p % P->out_w);
+    const int32_t v = pixels ? pixels[2 * p + 1] : (int32_t)(p / P->out_w);
+    double txx = 0.0, txy = 0.0, tyy = 0.0;
+    int count = 0;
+    for (int b = -q; b <= q; ++b) {
+      for (int a = -q; a <= q; ++a) {
+        const int uu = u + a, vv = v + b;
+        if (uu < 0 || vv < 0 || uu >= P->out_w || vv >= P->out_h) continue;
+        const double gx = grad_plane[2 * ((int64_t)vv * P->out_w + uu)];
+        const double gy = grad_plane[2 * ((int64_t)vv * P->out_w + uu) + 1];
+        txx += gx * gx;
+        txy += gx * gy;
+        tyy += gy * gy;
+        ++count;
+      }
+    }
+    /* eigen-decomposition of the 2x2 symmetric G^T G */
+    const double half_tr = 0.5 * (txx + tyy);
+    const double disc = sqrt(0.25 * (txx - tyy) * (txx - tyy) + txy * txy);
+    const double e1 = half_tr + disc;
+    const double e2 = half_tr - disc > 0.0 ? half_tr - disc : 0.0;
+    const double s1 = sqrt(e1), s2 = sqrt(e2);
+    const double phi = 0.5 * atan2(2.0 * txy, txx - tyy); /* first right singular vector (cos, sin) */
+    const double u1x = cos(phi), u1y = sin(phi);
+    const double v1 = -u1y, v2 = u1x;                      /* second right singular vector */
+    const double sigma = (s1 + A->lambda1) / (s2 + A->lambda1);
+    const double gamma = pow((s1 * s2 + A->lambda2) / (double)count, A->alpha);
+    double la = gamma * sigma, lb = gamma / sigma;
+    la = la < lo ? lo : (la > hi ? hi : la);
+    lb = lb < lo ? lo : (lb > hi ? hi : lb);
+    /* C = la u1 u1^T + lb v v^T = lb I + (la - lb) u1 u1^T (u1 u1^T + v v^T = I) */
+    C[3 * p] = lb + (la - lb) * u1x * u1x;
+    C[3 * p + 1] = (la - lb) * u1x * u1y;
+    C[3 * p + 2] = lb + (la - lb) * u1y * u1y;
+    if (diag) {
+      diag[5 * p] = s1;
+      diag[5 * p + 1] = s2;
+      diag[5 * p + 2] = atan(v1 / v2);
+      diag[5 * p + 3] = sigma;
+      diag[5 * p + 4] = gamma;
+    }
+  }
   return 0;
 }

@@ -133,6 +133,65 @@ int orc_cfa_channel(int32_t cfa, int32_t x, int32_t y);
 int orc_ici_select(int32_t n_scales, const double* yhat, const double* var, const int32_t* valid,
                    double gamma, double* margin_out, double* gap_out);
 
+/* ---------------------------------------------------------------------------
+ * Adaptive anisotropic LPA with colour-channel correlation (CALPA), Sec. 5.4
+ * and Sec. 5.5.  Three stages:
+ *   1. orc_gradients: the gradient C1 of an isotropic order >= 1 fit of the G
+ *      channel at every output pixel (Sec. 5.4 first step; Sec. 5.5: G only);
+ *   2. orc_steering: per output pixel, the local gradient matrix over the
+ *      (2q+1)^2 neighbouring output pixels, its two singular values s1 >= s2
+ *      and directions, and from them the steering matrix
+ *      C = gamma U diag(sigma, 1/sigma) U^T, sigma = (s1 + l1) / (s2 + l1),
+ *      gamma = ((s1 s2 + l2) / M)^alpha, elongated along the edge;
+ *   3. orc_reconstruct_steered: the LPA-ICI reconstruction of all channels
+ *      with the window exp(-d^T C d / h) - exp(-r^2 / h) on the ellipse
+ *      d^T C d < r^2 (C = I gives orc_reconstruct exactly).
+ * Readings (each listed with its reason in the design notes):
+ *   R18 the window exponent is d^T C d / h, not d^T (hC)^-1 d: with C built as
+ *       Sec. 5.4 writes it (large eigenvalue sigma*gamma across the edge), the
+ *       inverse would widen the window across edges, against the section's
+ *       stated intent and the steering kernels it cites;
+ *   R19 Lambda = Delta, and U Lambda U^T (the transpose the text omits);
+ *   R20 the gradient analysis window w is uniform over the (2q+1)^2 output
+ *       pixels around j that lie in the output grid; M is their number;
+ *       pixels whose gradient fit is invalid contribute a zero gradient;
+ *   R21 the eigenvalues gamma*sigma and gamma/sigma of C are clamped to
+ *       [1/kappa^2, kappa^2] so the support stays within kappa r of X_j
+ *       (the paper states no bound; a tile-staged implementation needs one);
+ *   R22 gradients come from the G channel at radius grad_radius (times
+ *       kappa_G, like every G window), order grad_order, isotropic window.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double alpha;        /* structure sensitivity (>= 0)                          */
+  double lambda1;      /* elongation regulariser (paper: 1)                     */
+  double lambda2;      /* scaling regulariser (paper: 0.001)                    */
+  double grad_radius;  /* radius of the gradient fit (reference units)          */
+  double grad_h;       /* its window parameter; <= 0 selects 2 r^2 / 9          */
+  double max_stretch;  /* kappa >= 1 (R21)                                      */
+  int32_t grad_order;  /* 1 or 2                                                */
+  int32_t grad_halfwin;/* q >= 0: analysis window of (2q+1)^2 output pixels     */
+} orc_adapt;
+
+/* Stage 1.  grad: 2 doubles per listed pixel (reference-plane units, zero
+ * where the fit is invalid); valid: optional, 1 per pixel.  pixels == NULL
+ * means the whole output grid in row-major order.  Returns 0 or < 0. */
+int orc_gradients(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
+                  const orc_params* params, const orc_adapt* adapt, const int32_t* pixels,
+                  int64_t n_pixels, double* grad, int32_t* valid);
+
+/* Stage 2 from a gradient plane covering the whole output grid (row-major,
+ * 2 doubles per pixel).  C: 3 doubles per listed pixel (cxx, cxy, cyy);
+ * diag: optional, 5 per pixel (s1, s2, theta, sigma, gamma). */
+int orc_steering(const orc_params* params, const orc_adapt* adapt, const double* grad_plane,
+                 const int32_t* pixels, int64_t n_pixels, double* C, double* diag);
+
+/* Stage 3 with given steering matrices (3 doubles per listed pixel; NULL
+ * means the identity).  Outputs as orc_reconstruct. */
+int orc_reconstruct_steered(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
+                            const orc_params* params, const double* C, const int32_t* pixels,
+                            int64_t n_pixels, double* rgb, uint8_t* scale_map, double* margin,
+                            double* gap, orc_fit* fits);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,13 +36,32 @@ MUTATIONS = [
     ("no equilibration", "At[i][j] = scale[i] * A[i][j] * scale[j];", "At[i][j] = A[i][j];"),
     ("back substitution index", "for (int k = i + 1; k < n; ++k) t -= L[k][i] * x[k];",
      "for (int k = i + 1; k < n; ++k) t -= L[i][k] * x[k];"),
-    ("box too small", "const double wx = r * sqrt(i00 * i00 + i01 * i01), wy = r * sqrt(i10 * i10 + i11 * i11);",
-     "const double wx = 0.5 * r * sqrt(i00 * i00 + i01 * i01), wy = 0.5 * r * sqrt(i10 * i10 + i11 * i11);"),
+    ("box too small", "const double wx = reff * sqrt(i00 * i00 + i01 * i01), wy = reff * sqrt(i10 * i10 + i11 * i11);",
+     "const double wx = 0.5 * reff * sqrt(i00 * i00 + i01 * i01), wy = 0.5 * reff * sqrt(i10 * i10 + i11 * i11);"),
     ("default h", "2.0 * P->radii[m] * P->radii[m] / 9.0", "2.0 * P->radii[m] * P->radii[m] / 4.5"),
     ("green ratio not applied to radius", "const double r = P->radii[m] * kappa;", "const double r = P->radii[m];"),
     ("CFA GRBG wrong", "{1, 0, 2, 1}, /* GRBG */", "{1, 2, 0, 1}, /* GRBG */"),
     ("variance sandwich uses A", "var += g[i] * B[i][j] * g[j];", "var += g[i] * A[i][j] * g[j];"),
     ("fallback skipped", "for (int o = M; o >= 0; --o) {", "for (int o = M; o >= M; --o) {"),
+    # adaptive anisotropic LPA / CALPA (Sec. 5.4, 5.5)
+    ("steered window uses C inverse",
+     "const double d2 = C ? C[0] * dx * dx + 2.0 * C[1] * dx * dy + C[2] * dy * dy : dx * dx + dy * dy;",
+     "const double d2 = C ? (C[2] * dx * dx - 2.0 * C[1] * dx * dy + C[0] * dy * dy) / (C[0] * C[2] - C[1] * C[1])"
+     " : dx * dx + dy * dy;"),
+    ("window elongated across the edge", "double la = gamma * sigma, lb = gamma / sigma;",
+     "double la = gamma / sigma, lb = gamma * sigma;"),
+    ("steering from the edge direction", "const double u1x = cos(phi), u1y = sin(phi);",
+     "const double u1x = -sin(phi), u1y = cos(phi);"),
+    ("elongation without lambda1", "const double sigma = (s1 + A->lambda1) / (s2 + A->lambda1);",
+     "const double sigma = (s1 + 1e-300) / (s2 + 1e-300);"),
+    ("scaling without the sample count", "pow((s1 * s2 + A->lambda2) / (double)count, A->alpha)",
+     "pow(s1 * s2 + A->lambda2, A->alpha)"),
+    ("analysis window short by a row", "for (int b = -q; b <= q; ++b) {", "for (int b = -q + 1; b <= q; ++b) {"),
+    ("steering eigenvalue not clamped", "la = la < lo ? lo : (la > hi ? hi : la);", "la = la * 1.0;"),
+    ("gradients of the R channel",
+     "gather_support(sensors, n_sensors, raw, X, Y, 1, r, h, NULL, P->exhaustive, &list)",
+     "gather_support(sensors, n_sensors, raw, X, Y, 0, r, h, NULL, P->exhaustive, &list)"),
+    ("ellipse box not widened", "reff = r / sqrt(lmin);", "reff = r;"),
 ]
 
 
@@ -63,6 +82,7 @@ def test_pins_catch_planted_mistake(name, orig, bad):
                         src, "-lm"], check=True)
         env = dict(os.environ, LPA_ORACLE_LIB_OVERRIDE=lib)
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                            os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_calpa.py")],
                            cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake '{name}' passed every pin:\n{r.stdout[-2000:]}"
