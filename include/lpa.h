@@ -111,7 +111,37 @@ typedef struct {
   double tau_inv;         /* validity threshold; <= 0 selects 1e-5                  */
   double tau_fp64;        /* order-2 solves with a smaller pivot are refined in FP64 (<= 0: 1e-3) */
   uint32_t flags;         /* LPA_FLAG_*                                             */
+  /* Adaptive anisotropic LPA with colour-channel correlation (CALPA, Sec. 5.4 and
+   * 5.5), used when mode == LPA_MODE_CALPA:
+   *   1. the gradient of an isotropic fit of the G channel (radius grad_radius,
+   *      scaled by green_ratio like every G window; order grad_order) at every
+   *      output pixel;
+   *   2. per output pixel, the singular values s1 >= s2 and directions of the
+   *      gradients of the (2 grad_halfwin + 1)^2 surrounding output pixels
+   *      give the steering matrix C = gamma U diag(sigma, 1/sigma) U^T, with
+   *      sigma = (s1 + lambda1) / (s2 + lambda1) across the edge,
+   *      gamma = ((s1 s2 + lambda2) / M)^alpha, M the pixels counted; both
+   *      eigenvalues are clamped to [1/max_stretch^2, max_stretch^2];
+   *   3. the order-M ICI reconstruction of R, G and B with the window
+   *      exp(-d^T C d / h) - exp(-r^2 / h) on the ellipse d^T C d < r^2.
+   * Zero values select: grad_radius the second radius (the first if there is
+   * one), grad_h 2 r^2 / 9, max_stretch 2, grad_order 1.  lambda1, lambda2
+   * are in the units of the squared gradient (radiance per reference pixel);
+   * the paper uses 1 and 0.001.  CALPA frames are reconstructed per frame
+   * (lpa_reconstruct, lpa_reconstruct_plain); batches and lpa_submit reject
+   * them with LPA_ERR_UNSUPPORTED. */
+  int32_t mode;           /* LPA_MODE_*                                             */
+  int32_t grad_order;     /* 1 or 2 (0: 1)                                          */
+  int32_t grad_halfwin;   /* >= 0                                                   */
+  int32_t pad_;
+  double alpha;           /* structure sensitivity >= 0                             */
+  double lambda1, lambda2;/* >= 0                                                   */
+  double grad_radius;     /* reference-plane units (<= 0: default)                  */
+  double grad_h;          /* <= 0: 2 grad_radius^2 / 9                              */
+  double max_stretch;     /* >= 1 (0: 2)                                            */
 } lpa_params;
+
+enum { LPA_MODE_LPA = 0, LPA_MODE_CALPA = 1 };
 
 /* One frame: a raw plane per sensor (row-major, row_pitch_bytes apart). */
 typedef struct {
@@ -134,6 +164,13 @@ typedef struct {
   int64_t scale_map_pitch;    /* bytes between scale_map rows    */
   float* sd_map;              /* may be NULL                     */
   int64_t sd_map_pitch;       /* bytes between sd_map rows       */
+  /* CALPA only, both optional: the G gradient of every output pixel (2 floats,
+   * reference-plane units, zero where its fit is invalid) and the steering
+   * matrix (4 floats: cxx, cxy, cyy, 0). */
+  float* grad_map;
+  int64_t grad_map_pitch;
+  float* steer_map;
+  int64_t steer_map_pitch;
 } lpa_output;
 
 /* Status and timestamps of a submitted frame (CLOCK_MONOTONIC ns). */
@@ -200,7 +237,8 @@ lpa_status lpa_drain(lpa_ctx* ctx);
 
 /* Autotuning (launch shape only; results never depend on it).  Candidates:
  * tile shapes 16x16, 32x8, 8x32, 64x4 output pixels (256 lanes; a wavefront
- * covers 16x4, 32x2, 8x8 or 64x1 pixels) times two register budgets for
+ * holds one 2x2 parity class of the tile: 8x8, 16x4, 4x16 or 32x2 pixels two
+ * apart) times two register budgets for
  * order-2 fits (3 or 4 waves per SIMD).  Each candidate is launched on the
  * given frame `reps` times on `hip_stream` (writing `out`), timed with HIP
  * events; the fastest becomes the choice for every frame of the same class

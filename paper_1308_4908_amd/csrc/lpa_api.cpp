@@ -102,6 +102,25 @@ lpa_status resolve_params(const lpa_params* p, Resolved* r) {
   r->tau_fp64 = p->tau_fp64 > 0 ? p->tau_fp64 : 1e-3;
   r->gamma = p->n_scales > 1 ? p->gamma : 1.0;
   for (int m = 0; m < p->n_scales; ++m) r->h[m] = p->h[m] > 0 ? p->h[m] : 2.0 * p->radii[m] * p->radii[m] / 9.0;
+  if (p->mode != LPA_MODE_LPA && p->mode != LPA_MODE_CALPA)
+    return set_error(LPA_ERR_INVALID_ARG, "mode %d invalid", p->mode);
+  if (p->mode == LPA_MODE_CALPA) {
+    const double vals[] = {p->alpha, p->lambda1, p->lambda2, p->grad_radius, p->grad_h, p->max_stretch};
+    for (double v : vals)
+      if (!std::isfinite(v)) return set_error(LPA_ERR_INVALID_ARG, "adaptive parameters not finite");
+    if (!(p->alpha >= 0) || !(p->lambda1 >= 0) || !(p->lambda2 >= 0))
+      return set_error(LPA_ERR_INVALID_ARG, "alpha, lambda1 and lambda2 must be >= 0");
+    if (p->grad_order < 0 || p->grad_order > 2)
+      return set_error(LPA_ERR_INVALID_ARG, "grad_order %d invalid", p->grad_order);
+    if (p->grad_halfwin < 0 || p->grad_halfwin > 16)
+      return set_error(LPA_ERR_INVALID_ARG, "grad_halfwin %d invalid (0..16)", p->grad_halfwin);
+    if (p->max_stretch != 0 && !(p->max_stretch >= 1 && p->max_stretch <= 8))
+      return set_error(LPA_ERR_INVALID_ARG, "max_stretch %g invalid (1..8)", p->max_stretch);
+    r->grad_order = p->grad_order == 0 ? 1 : p->grad_order;
+    r->grad_radius = p->grad_radius > 0 ? p->grad_radius : p->radii[p->n_scales > 1 ? 1 : 0];
+    r->grad_h = p->grad_h > 0 ? p->grad_h : 2.0 * r->grad_radius * r->grad_radius / 9.0;
+    r->max_stretch = p->max_stretch == 0 ? 2.0 : p->max_stretch;
+  }
   return LPA_OK;
 }
 
@@ -129,6 +148,14 @@ lpa_status validate_output(const lpa_params* p, const lpa_output* o) {
     return set_error(LPA_ERR_INVALID_ARG, "scale_map pitch %lld invalid", (long long)o->scale_map_pitch);
   if (o->sd_map && (o->sd_map_pitch < (int64_t)12 * p->out_w || o->sd_map_pitch % 4))
     return set_error(LPA_ERR_INVALID_ARG, "sd_map pitch %lld invalid", (long long)o->sd_map_pitch);
+  if (o->grad_map && (o->grad_map_pitch < (int64_t)8 * p->out_w || o->grad_map_pitch % 8 ||
+                      reinterpret_cast<uintptr_t>(o->grad_map) % 8))
+    return set_error(LPA_ERR_INVALID_ARG, "grad_map pitch %lld or alignment invalid", (long long)o->grad_map_pitch);
+  if (o->steer_map && (o->steer_map_pitch < (int64_t)16 * p->out_w || o->steer_map_pitch % 16 ||
+                       reinterpret_cast<uintptr_t>(o->steer_map) % 16))
+    return set_error(LPA_ERR_INVALID_ARG, "steer_map pitch %lld or alignment invalid", (long long)o->steer_map_pitch);
+  if ((o->grad_map || o->steer_map) && p->mode != LPA_MODE_CALPA)
+    return set_error(LPA_ERR_INVALID_ARG, "grad_map and steer_map are CALPA outputs");
   return LPA_OK;
 }
 
@@ -207,6 +234,7 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output*
       const double h = R.h[m] * kappa * kappa;
       const double cs = std::sqrt(1.4426950408889634 / h);
       K->sc[m].radius[cls] = r;
+      K->sc[m].box_radius[cls] = r * R.box_stretch;
       K->sc[m].coord_scale[cls] = (float)cs;
       const double reach = (double)(float)cs * r * (1 + 1e-4);
       K->sc[m].reach2[cls] = (float)(reach * reach);
@@ -223,8 +251,8 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output*
     double wmx = 0, wmy = 0;
     for (int cls = 0; cls < 2; ++cls) {
       for (int m = 0; m < p.n_scales; ++m) {
-        const double wx = K->sc[m].radius[cls] * S.rownorm[0];
-        const double wy = K->sc[m].radius[cls] * S.rownorm[1];
+        const double wx = K->sc[m].box_radius[cls] * S.rownorm[0];
+        const double wy = K->sc[m].box_radius[cls] * S.rownorm[1];
         const double nx = std::max(1.0, std::ceil(wx - 1e-9));
         const double ny = std::max(1.0, std::ceil(wy - 1e-9));
         if (nx > 120 || ny > 120)
@@ -331,6 +359,110 @@ lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_
   return LPA_OK;
 }
 
+// Adaptive anisotropic LPA with colour-channel correlation (Sec. 5.4, 5.5):
+// gradient pass (G channel, isotropic), steering pass, steered fit of R, G, B.
+// Every descriptor is built and checked before anything is enqueued.
+static lpa_status calpa_impl(lpa_rig* rig, const lpa_frame* frame, const Resolved& R, const lpa_output* out,
+                             hipStream_t hs, bool plain) {
+  lpa_ctx* ctx = rig->ctx;
+  const int storage = plain ? LPA_STORE_FP32 : R.p.storage;
+  int src_kind;
+  const void* srcs[LPA_MAX_SENSORS];
+  int64_t pitches[LPA_MAX_SENSORS];
+  void* planes[LPA_MAX_SENSORS] = {nullptr};
+  size_t plane_bytes[LPA_MAX_SENSORS] = {0};
+  if (storage == LPA_STORE_FUSED) {
+    src_kind = frame->dtype == LPA_DTYPE_U16 ? SRC_RAW_U16 : SRC_RAW_F32;
+    for (int s = 0; s < rig->n; ++s) {
+      srcs[s] = frame->raw[s];
+      pitches[s] = frame->row_pitch_bytes[s];
+    }
+  } else {
+    src_kind = storage == LPA_STORE_FP16 ? SRC_PLANE_F16 : SRC_PLANE_F32;
+    for (int s = 0; s < rig->n; ++s) {
+      srcs[s] = nullptr;
+      pitches[s] = 0;
+    }
+  }
+  // gradient pass: one isotropic radius, order grad_order, no variance
+  Resolved Rg = R;
+  Rg.p.order = R.grad_order;
+  Rg.p.n_scales = 1;
+  Rg.p.radii[0] = R.grad_radius;
+  Rg.p.h[0] = R.grad_h;
+  Rg.h[0] = R.grad_h;
+  Rg.box_stretch = 1;
+  lpa_output og{};
+  og.rgb = out->rgb;
+  og.row_pitch_bytes = out->row_pitch_bytes;
+  LaunchK Kg, Ks;
+  lpa_status st = build_launch_fit(rig, Rg, &og, src_kind, srcs, pitches, 16, 16, &Kg);
+  if (st != LPA_OK) return st;
+  // steered fit: boxes cover the ellipse, within max_stretch * r of the pixel
+  Resolved Rs = R;
+  Rs.box_stretch = R.max_stretch;
+  if ((st = build_launch_fit(rig, Rs, out, src_kind, srcs, pitches, 16, 16, &Ks)) != LPA_OK) return st;
+
+  const int W = R.p.out_w, H = R.p.out_h;
+  void* gbuf = nullptr;
+  void* sbuf = nullptr;
+  const size_t gbytes = (size_t)W * H * 8, sbytes = (size_t)W * H * 16;
+  float* gptr = out->grad_map;
+  int64_t gpitch = out->grad_map_pitch;
+  float* sptr = out->steer_map;
+  int64_t spitch = out->steer_map_pitch;
+  if (!gptr) {
+    if ((st = alloc_async(ctx, gbytes, hs, &gbuf)) != LPA_OK) return st;
+    gptr = static_cast<float*>(gbuf);
+    gpitch = (int64_t)W * 8;
+  }
+  if (!sptr) {
+    if ((st = alloc_async(ctx, sbytes, hs, &sbuf)) != LPA_OK) {
+      free_async(ctx, gbuf, gbytes, hs);
+      return st;
+    }
+    sptr = static_cast<float*>(sbuf);
+    spitch = (int64_t)W * 16;
+  }
+  if (storage != LPA_STORE_FUSED) {
+    st = run_prepass(rig, frame, storage == LPA_STORE_FP16, hs, planes, plane_bytes, srcs, pitches);
+    if (st == LPA_OK)
+      for (int s = 0; s < rig->n; ++s) {
+        Kg.s[s].src = Ks.s[s].src = srcs[s];
+        Kg.s[s].pitch = Ks.s[s].pitch = pitches[s];
+      }
+  }
+  Kg.grad = gptr;
+  Kg.grad_pitch = gpitch;
+  Kg.map = nullptr;
+  Kg.sd = nullptr;
+  Kg.need_var = 0;
+  if (st == LPA_OK && lpa_k_grad(&Kg, hs) != 0) st = device_error(ctx, hipGetLastError(), "gradient launch");
+  if (st == LPA_OK) {
+    SteerArgs A{};
+    A.grad = gptr;
+    A.grad_pitch = gpitch;
+    A.steer = sptr;
+    A.steer_pitch = spitch;
+    A.out_w = W;
+    A.out_h = H;
+    A.q = R.p.grad_halfwin;
+    A.alpha = R.p.alpha;
+    A.lambda1 = R.p.lambda1;
+    A.lambda2 = R.p.lambda2;
+    A.lo = 1.0 / (R.max_stretch * R.max_stretch);
+    A.hi = R.max_stretch * R.max_stretch;
+    if (lpa_k_steer(&A, hs) != 0) st = device_error(ctx, hipGetLastError(), "steering launch");
+  }
+  Ks.steer = sptr;
+  Ks.steer_pitch = spitch;
+  if (st == LPA_OK && lpa_k_fit_steered(&Ks, hs) != 0) st = device_error(ctx, hipGetLastError(), "steered fit launch");
+  for (int s = 0; s < rig->n; ++s) free_async(ctx, planes[s], plane_bytes[s], hs);
+  free_async(ctx, gbuf, gbytes, hs);
+  free_async(ctx, sbuf, sbytes, hs);
+  return st;
+}
+
 lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
                             const lpa_output* out, void* stream, bool plain) {
   if (!rig) return set_error(LPA_ERR_INVALID_ARG, "rig is NULL");
@@ -344,6 +476,7 @@ lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_para
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return device_error(ctx, e, "hipSetDevice");
   hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (R.p.mode == LPA_MODE_CALPA) return calpa_impl(rig, frame, R, out, hs, plain);
 
   const int storage = plain ? LPA_STORE_FP32 : R.p.storage;
   int src_kind;

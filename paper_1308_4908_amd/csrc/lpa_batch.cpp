@@ -40,6 +40,8 @@ lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_f
   for (int i = 0; i < n; ++i) {
     if (!rigs[i] || rigs[i]->ctx != ctx) return set_error(LPA_ERR_INVALID_ARG, "frame %d: rig missing or from another context", i);
     lpa_status st = resolve_params(&params[i], &Rs[i]);
+    if (st == LPA_OK && Rs[i].p.mode != LPA_MODE_LPA)
+      st = set_error(LPA_ERR_UNSUPPORTED, "frame %d: CALPA frames are reconstructed per frame", i);
     if (st == LPA_OK) st = validate_frame(rigs[i], &frames[i], true);
     if (st == LPA_OK) st = validate_output(&params[i], &outs[i]);
     if (st != LPA_OK) return set_error(st, "frame %d: %s", i, g_last_error);

@@ -25,6 +25,11 @@ struct Resolved {
   lpa_params p;
   double tau_inv, tau_fp64, gamma;
   double h[LPA_MAX_SCALES];
+  // CALPA (mode == LPA_MODE_CALPA), defaults applied
+  double grad_radius = 0, grad_h = 0, max_stretch = 1;
+  int grad_order = 1;
+  // support boxes cover radius * box_stretch (max_stretch for the steered fit)
+  double box_stretch = 1;
 };
 
 // Class of a frame for tuning: everything that changes the kernel's cost per

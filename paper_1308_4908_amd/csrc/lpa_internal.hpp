@@ -45,6 +45,7 @@ struct SensorK {
 // Per-scale constants, per channel class (0: R and B, 1: G).
 struct ScaleK {
   double radius[2];   // r' = r * kappa_class
+  double box_radius[2]; // half-width of the support box: r', or r' times the stretch bound of steered windows
   float coord_scale[2]; // s = sqrt(log2(e) / h'): exp(-|d|^2 / h') = exp2(-|s d|^2)
   float reach2[2];    // (s r' (1 + 1e-4))^2: samples at or beyond it have exactly zero weight
   float e_edge[2];    // exp(-r'^2 / h'): subtracted so the window vanishes at r'
@@ -69,6 +70,10 @@ struct LaunchK {
   int64_t map_pitch;        // bytes
   float* sd;                // optional standard deviation of each output value
   int64_t sd_pitch;         // bytes
+  const float* steer;       // steered fit: per output pixel (cxx, cxy, cyy, 0) of the window d^T C d
+  int64_t steer_pitch;      // bytes
+  float* grad;              // gradient pass: per output pixel (df/dX, df/dY), reference-plane units
+  int64_t grad_pitch;       // bytes
   SensorK s[kMaxSensors];
   ScaleK sc[kMaxScales];
 };
@@ -89,6 +94,18 @@ inline void lane_pixel(int tid, int tw, int th, int* du, int* dv) {
   *du = 2 * (w % hw) + (cls & 1);
   *dv = 2 * (w / hw) + (cls >> 1);
 }
+
+// Steering pass (adaptive anisotropic windows): per output pixel, the
+// structure of the gradients of the (2q+1)^2 surrounding pixels.
+struct SteerArgs {
+  const float* grad;        // (df/dX, df/dY) per output pixel
+  int64_t grad_pitch;       // bytes
+  float* steer;             // (cxx, cxy, cyy, 0) per output pixel
+  int64_t steer_pitch;      // bytes
+  int32_t out_w, out_h, q, pad_;
+  double alpha, lambda1, lambda2;
+  double lo, hi;            // eigenvalue clamp [1/kappa^2, kappa^2]
+};
 
 // Header of a batch table in device memory (read by the persistent kernel, so
 // a captured graph can be replayed with new table contents).
@@ -115,6 +132,13 @@ int lpa_k_fit_batch(const lpa::BatchHeader* d_hdr, const lpa::LaunchK* d_frames,
                     const int64_t* d_first_tile, int32_t* d_queue, int32_t src_kind, int32_t block,
                     int32_t lds_floats2, int32_t grid, void* stream);
 int lpa_k_fit_max_lds_bytes(void);
+// Gradient pass: K.order (1 or 2) fit of the G channel at radius K.sc[0] (no
+// ICI) writing K.grad.
+int lpa_k_grad(const lpa::LaunchK* k, void* stream);
+// Steering pass over the gradient plane.
+int lpa_k_steer(const lpa::SteerArgs* a, void* stream);
+// Fit with per-pixel steered windows read from K.steer.
+int lpa_k_fit_steered(const lpa::LaunchK* k, void* stream);
 // Zero n ints with a small kernel (graph-safe replacement for a memset).
 int lpa_k_zero_i32(int32_t* p, int32_t n, void* stream);
 }

@@ -58,11 +58,23 @@ __device__ __forceinline__ void acc_zero(Acc<ORDER, ICI>& a) {
 // vanish at the radius and clamped to zero beyond it.  A sample at or beyond
 // reach2 has exactly zero weight, so the update is skipped there: per lane,
 // and for the whole wave when none of its lanes has the sample in its window.
-template <int ORDER, bool ICI>
+// A steered window (adaptive anisotropic LPA, Sec. 5.4) replaces |d|^2 by
+// the quadratic form d^T C d of the pixel's steering matrix.
+struct SteerC {
+  float cxx, cyy, c2xy;  // C_xx, C_yy, 2 C_xy
+};
+
+template <bool STEER>
+__device__ __forceinline__ float window_r2(float dx, float dy, float x2, float y2, const SteerC& sc) {
+  if constexpr (STEER) return __builtin_fmaf(sc.cxx, x2, __builtin_fmaf(sc.cyy, y2, sc.c2xy * (dx * dy)));
+  else return x2 + y2;
+}
+
+template <int ORDER, bool ICI, bool STEER>
 __device__ __forceinline__ void acc_sample(Acc<ORDER, ICI>& a, float dx, float dy, float f, float iv,
-                                           float e_edge, float reach2) {
+                                           float e_edge, float reach2, const SteerC& sc) {
   const float x2 = dx * dx, y2 = dy * dy;
-  const float r2 = x2 + y2;
+  const float r2 = window_r2<STEER>(dx, dy, x2, y2, sc);
   if (r2 < reach2) {
     float mono[n_mom<ORDER>()];
     mono[0] = 1.f;
@@ -220,6 +232,45 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T
     // Provisional: the caller also requires >= no samples where rho alone
     // does not certify it.
     out.ok[o] = diag_all && (rho >= tau);
+  }
+}
+
+// Equilibrated pivots of the leading blocks (orders 0..ORDER), in FP64, of a
+// normal matrix re-accumulated in FP64.  Where a pivot is small, the pivots
+// after it carry the rounding of FP32 moments amplified by its inverse: the
+// samples of a support lying on one line (one sensor column, say) give an
+// exactly singular matrix whose FP32 moments can look regular, with a pivot
+// far above tau.  The FP32 factorization decides every fit whose pivots all
+// stay above kPivotCertifiesN (rounding cannot bring them to tau); the
+// others are decided on these pivots.
+template <int ORDER>
+__device__ __forceinline__ void pivots_fp64(const double* m, double* rho_o) {
+  constexpr int NB = n_basis<ORDER>();
+  constexpr int nb_tab[3] = {1, 3, 6};
+  double L[NB][NB], D[NB];
+  double rho = 1e300;
+  int o = 0;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const double ajj = m[aidx(j, j)];
+    double d = ajj;
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k] * D[k];
+    D[j] = d;
+    const double req = ajj > 0.0 ? d / ajj : 0.0;
+    rho = req < rho ? req : rho;
+    const double id = d > 0.0 ? 1.0 / d : 0.0;
+#pragma unroll
+    for (int i = j + 1; i < NB; ++i) {
+      double t = m[aidx(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k] * D[k];
+      L[i][j] = t * id;
+    }
+    if (j == nb_tab[o] - 1) {
+      rho_o[o] = rho > 0.0 ? rho : 0.0;
+      ++o;
+    }
   }
 }
 
@@ -402,10 +453,12 @@ __device__ __forceinline__ void stage_tile(const LaunchK& K, int u0, int v0, flo
 // carry ~1e-4 relative error or less in FP32; below it the moment form's
 // cancellation grows quickly.
 //
-// A support of fewer than n_o samples makes the normal matrix singular, whose
-// equilibrated FP32 pivot then stays within ~N u of zero; a pivot of at least
-// kPivotCertifiesN therefore certifies N >= n_o, and only fits below it have
-// their samples counted (in the same second pass).
+// An FP32 pivot carries the moments' rounding amplified by the inverse of the
+// pivots before it.  While every pivot of a fit stays above kPivotCertifiesN
+// that error is far below tau and below the pivot itself, so the FP32
+// factorization decides the fit, and its matrix being regular certifies
+// N >= n_o.  A fit with a smaller pivot is decided by the second pass: its
+// samples are counted and its normal matrix re-accumulated in FP64.
 constexpr float kPivotCertifiesN = 1e-3f;
 
 // Visits an nx x ny box of sub-lattice points in blocks of kBlk x kBlk: the
@@ -452,7 +505,7 @@ template <class Fn>
 __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds, const Region* regs,
                                              double Xj, double Yj, int c, int cls, int m, Fn&& fn) {
   const ScaleK& SC = K.sc[m];
-  const double rad = SC.radius[cls];
+  const double rad = SC.box_radius[cls];
   const float cs = SC.coord_scale[cls];
   for (int s = 0; s < K.n_sensors; ++s) {
     const SensorK& S = K.s[s];
@@ -486,11 +539,19 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
   }
 }
 
-template <int ORDER, bool ICI>
+template <int ORDER, bool ICI, bool STEER>
 __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, const Region* regs,
                                           int u, int v, bool active) {
   const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
   const double Yj = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
+  SteerC sc = {1.f, 1.f, 0.f};  // lanes outside the grid keep the isotropic window (inside the box)
+  if constexpr (STEER) {
+    if (active) {
+      const float4 c = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(K.steer) +
+                                                       (int64_t)v * K.steer_pitch)[u];
+      sc = {c.x, c.z, 2.f * c.y};
+    }
+  }
   for (int c = 0; c < 3; ++c) {
     const int cls = (c == 1) ? 1 : 0;
     IciState st[ORDER + 1];
@@ -503,7 +564,7 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
       Acc<ORDER, ICI> a;
       acc_zero(a);
       auto accumulate = [&](float dx, float dy, float f, float iv) {
-        acc_sample<ORDER, ICI>(a, dx, dy, f, iv, eedge, reach2);
+        acc_sample<ORDER, ICI, STEER>(a, dx, dy, f, iv, eedge, reach2, sc);
       };
       walk_support(K, lds, regs, Xj, Yj, c, cls, m, accumulate);
 
@@ -518,27 +579,55 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
         if (K.use_fp64 && fr.ok[2] && fr.rho[2] < K.tau_fp64) refine_order2(a.m, a.b, fr.g[2], fr.y[2]);
       }
       if constexpr (ORDER >= 1) {
-        // Second pass, taken by the whole wave when any lane needs it: count
-        // the samples of fits whose pivot does not certify N >= n_o, and
-        // recompute the variance of ill-conditioned fits from positive terms.
-        bool need = false;
+        // Second pass over the samples, taken by the whole wave when any lane
+        // needs it:
+        //  - fits whose FP32 pivot is small are counted and their normal
+        //    matrix re-accumulated in FP64; their validity is decided on its
+        //    FP64 pivots (see pivots_fp64);
+        //  - ill-conditioned valid fits get their variance from positive terms.
+        bool small = false, need_var = false;
 #pragma unroll
-        for (int o = 1; o <= ORDER; ++o)
-          need = need || (fr.ok[o] && (fr.rho[o] < kPivotCertifiesN || (ICI && fr.rho[o] < K.tau_fp64)));
-        if (__builtin_amdgcn_ballot_w64(need) != 0) {
+        for (int o = 1; o <= ORDER; ++o) {
+          small = small || ((o == ORDER || lower) && fr.rho[o] < kPivotCertifiesN);
+          need_var = need_var || (ICI && fr.ok[o] && fr.rho[o] < K.tau_fp64);
+        }
+        if (__builtin_amdgcn_ballot_w64(small || need_var) != 0) {
           int n = 0;
+          double m64[n_mom<ORDER>()];
+#pragma unroll
+          for (int k = 0; k < n_mom<ORDER>(); ++k) m64[k] = 0.0;
           float vs[ORDER + 1];
 #pragma unroll
           for (int o = 0; o <= ORDER; ++o) vs[o] = 0.f;
           auto second = [&](float dx, float dy, float f, float iv) {
             (void)f;
             const float x2 = dx * dx, y2 = dy * dy;
-            const float r2 = x2 + y2;
+            const float r2 = window_r2<STEER>(dx, dy, x2, y2, sc);
             if (r2 < reach2) {
               const float kw = fmaxf(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f);
-              n += (kw * iv > 0.f) ? 1 : 0;
+              const float w = kw * iv;
+              n += (w > 0.f) ? 1 : 0;
+              const double wd = w, x = dx, y = dy;
+              const double xx = x * x, xy = x * y, yy = y * y;
+              m64[0] += wd;
+              m64[1] += wd * x;
+              m64[2] += wd * y;
+              m64[3] += wd * xx;
+              m64[4] += wd * xy;
+              m64[5] += wd * yy;
+              if constexpr (ORDER >= 2) {
+                m64[6] += wd * xx * x;
+                m64[7] += wd * xx * y;
+                m64[8] += wd * xy * y;
+                m64[9] += wd * yy * y;
+                m64[10] += wd * xx * xx;
+                m64[11] += wd * xx * xy;
+                m64[12] += wd * xx * yy;
+                m64[13] += wd * xy * yy;
+                m64[14] += wd * yy * yy;
+              }
               if constexpr (ICI) {
-                const float w2 = kw * kw * iv;
+                const float w2 = w * kw;
                 float phi[6] = {1.f, dx, dy, x2, dx * dy, y2};
 #pragma unroll
                 for (int o = 1; o <= ORDER; ++o) {
@@ -552,10 +641,18 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
             }
           };
           walk_support(K, lds, regs, Xj, Yj, c, cls, m, second);
+          double r64[ORDER + 1];
+          pivots_fp64<ORDER>(m64, r64);
 #pragma unroll
           for (int o = 1; o <= ORDER; ++o) {
             constexpr int nb_tab[3] = {1, 3, 6};
-            if (fr.rho[o] < kPivotCertifiesN && n < nb_tab[o]) fr.ok[o] = false;
+            if ((o == ORDER || lower) && fr.rho[o] < kPivotCertifiesN) {
+              bool diag = true;
+#pragma unroll
+              for (int i = 0; i < nb_tab[o]; ++i) diag = diag && m64[aidx(i, i)] > 0.0;
+              fr.rho[o] = diag ? (float)r64[o] : 0.f;
+              fr.ok[o] = diag && r64[o] >= (double)K.tau_inv && n >= nb_tab[o];
+            }
             if constexpr (ICI)
               if (fr.rho[o] < K.tau_fp64) fr.v[o] = vs[o];
           }
@@ -590,7 +687,7 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
   }
 }
 
-template <int ORDER, bool ICI, int SRC>
+template <int ORDER, bool ICI, int SRC, bool STEER = false>
 __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2* lds, Region* regs) {
   const int tx = tile % K.tiles_x;
   const int ty = tile / K.tiles_x;
@@ -604,7 +701,7 @@ __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2*
   const int u = u0 + du, v = v0 + dv;
   const bool active = (u < K.out_w) && (v < K.out_h);
   // inactive lanes of a ragged tile compute at their nominal pixel (staged)
-  fit_pixel<ORDER, ICI>(K, lds, regs, u, v, active);
+  fit_pixel<ORDER, ICI, STEER>(K, lds, regs, u, v, active);
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup i runs on
@@ -634,6 +731,188 @@ fit_kernel_occ4(const LaunchK K) {
   extern __shared__ float2 lds[];
   __shared__ Region regs[kMaxSensors];
   process_tile<ORDER, ICI, SRC>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive anisotropic LPA with colour-channel correlation (Sec. 5.4, 5.5).
+// ---------------------------------------------------------------------------
+
+// Fit with per-pixel steered windows (the boxes cover the stretched ellipse).
+template <int ORDER, bool ICI, int SRC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+fit_kernel_steer(const LaunchK K) {
+  extern __shared__ float2 lds[];
+  __shared__ Region regs[kMaxSensors];
+  process_tile<ORDER, ICI, SRC, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
+}
+
+// Full coefficient vector of one fit in FP64: LDL^T of A (as in solve_fits),
+// then A C = b.  Returns C1 = (C[1], C[2]), the smallest equilibrated pivot
+// and whether every diagonal entry is positive.
+template <int ORDER>
+__device__ __forceinline__ void solve_gradient(const double* m, const double* b, double& c1x, double& c1y,
+                                               double& rho, bool& diag_all) {
+  constexpr int NB = n_basis<ORDER>();
+  double L[NB][NB], U[NB][NB], iD[NB];
+  rho = 1e300;
+  diag_all = true;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const double ajj = m[aidx(j, j)];
+    diag_all = diag_all && ajj > 0.0;
+    double d = ajj;
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= U[j][k] * L[j][k];
+    iD[j] = d > 0.0 ? 1.0 / d : 0.0;
+    const double req = ajj > 0.0 ? d / ajj : 0.0;
+    rho = req < rho ? req : rho;
+#pragma unroll
+    for (int i = j + 1; i < NB; ++i) {
+      double t = m[aidx(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= U[i][k] * L[j][k];
+      U[i][j] = t;
+      L[i][j] = t * iD[j];
+    }
+  }
+  double z[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    double t = b[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) t -= L[i][k] * z[k];
+    z[i] = t;
+  }
+  double C[NB];
+#pragma unroll
+  for (int i = NB - 1; i >= 0; --i) {
+    double t = z[i] * iD[i];
+#pragma unroll
+    for (int k = i + 1; k < NB; ++k) t -= L[k][i] * C[k];
+    C[i] = t;
+  }
+  c1x = C[1];
+  c1y = C[2];
+  if (!diag_all || !(rho > 0.0)) rho = 0.0;
+}
+
+// Gradient pass (Sec. 5.4 first step, G channel as in Sec. 5.5): isotropic
+// order-1 or order-2 fit of the G channel at radius K.sc[0]; its C1 in
+// reference-plane units (the fit ran in coordinates scaled by s), zero where
+// the fit is invalid.  Its moments are accumulated and solved in FP64: every
+// gradient feeds the steering of the (2q+1)^2 pixels around it, and FP32
+// rounding of an ill-conditioned gradient fit would move all their windows.
+// The pass is one channel at one radius, a small part of the whole.
+template <int ORDER, int SRC>
+__global__ void __launch_bounds__(256) grad_kernel(const LaunchK K) {
+  extern __shared__ float2 lds[];
+  __shared__ Region regs[kMaxSensors];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int u0 = (tile % K.tiles_x) * K.tile_w, v0 = (tile / K.tiles_x) * K.tile_h;
+  const int tid = threadIdx.x;
+  stage_tile<SRC>(K, u0, v0, lds, regs, tid, K.tile_w * K.tile_h);
+  __syncthreads();
+  int du, dv;
+  lane_pixel(tid, K.tile_w, K.tile_h, &du, &dv);
+  const int u = u0 + du, v = v0 + dv;
+  const bool active = (u < K.out_w) && (v < K.out_h);
+  const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
+  const double Yj = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
+  const float eedge = K.sc[0].e_edge[1];
+  const float reach2 = K.sc[0].reach2[1];
+  double m64[n_mom<ORDER>()], b64[n_basis<ORDER>()];
+#pragma unroll
+  for (int k = 0; k < n_mom<ORDER>(); ++k) m64[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < n_basis<ORDER>(); ++k) b64[k] = 0.0;
+  int n = 0;
+  auto accumulate = [&](float dx, float dy, float f, float iv) {
+    const float r2 = dx * dx + dy * dy;
+    if (r2 < reach2) {
+      const float w = fmaxf(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f) * iv;
+      n += (w > 0.f) ? 1 : 0;
+      const double wd = w, x = dx, y = dy, wf = wd * (double)f;
+      const double xx = x * x, xy = x * y, yy = y * y;
+      m64[0] += wd;
+      m64[1] += wd * x;
+      m64[2] += wd * y;
+      m64[3] += wd * xx;
+      m64[4] += wd * xy;
+      m64[5] += wd * yy;
+      b64[0] += wf;
+      b64[1] += wf * x;
+      b64[2] += wf * y;
+      if constexpr (ORDER >= 2) {
+        m64[6] += wd * xx * x;
+        m64[7] += wd * xx * y;
+        m64[8] += wd * xy * y;
+        m64[9] += wd * yy * y;
+        m64[10] += wd * xx * xx;
+        m64[11] += wd * xx * xy;
+        m64[12] += wd * xx * yy;
+        m64[13] += wd * xy * yy;
+        m64[14] += wd * yy * yy;
+        b64[3] += wf * xx;
+        b64[4] += wf * xy;
+        b64[5] += wf * yy;
+      }
+    }
+  };
+  walk_support(K, lds, regs, Xj, Yj, 1, 1, 0, accumulate);
+  double c1x, c1y, rho;
+  bool diag_all;
+  solve_gradient<ORDER>(m64, b64, c1x, c1y, rho, diag_all);
+  const bool ok = diag_all && rho >= (double)K.tau_inv && n >= n_basis<ORDER>();
+  if (active) {
+    const double s = K.sc[0].coord_scale[1];
+    float2* row = reinterpret_cast<float2*>(reinterpret_cast<char*>(K.grad) + (int64_t)v * K.grad_pitch);
+    row[u] = ok ? make_float2((float)(c1x * s), (float)(c1y * s)) : make_float2(0.f, 0.f);
+  }
+}
+
+// Steering pass (Sec. 5.4): the gradients of the (2q+1)^2 output pixels around
+// (u, v) inside the grid form G; the eigen-decomposition of G^T G gives its
+// singular values s1 >= s2 and the dominant gradient direction u1.  The
+// steering matrix C = gamma U diag(sigma, 1/sigma) U^T has eigenvalue
+// gamma*sigma along u1 (across the edge) and gamma/sigma along the edge, each
+// clamped to [lo, hi]; it is formed as lb I + (la - lb) u1 u1^T.  FP64: the
+// near-rank-1 structure tensors of edges would lose s2 to cancellation.
+__global__ void __launch_bounds__(256) steer_kernel(const SteerArgs A) {
+  const int u = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int v = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (u >= A.out_w || v >= A.out_h) return;
+  double txx = 0.0, txy = 0.0, tyy = 0.0;
+  int count = 0;
+  for (int b = -A.q; b <= A.q; ++b) {
+    const int vv = v + b;
+    if (vv < 0 || vv >= A.out_h) continue;
+    const float2* row = reinterpret_cast<const float2*>(reinterpret_cast<const char*>(A.grad) + (int64_t)vv * A.grad_pitch);
+    for (int a = -A.q; a <= A.q; ++a) {
+      const int uu = u + a;
+      if (uu < 0 || uu >= A.out_w) continue;
+      const float2 g = row[uu];
+      const double gx = g.x, gy = g.y;
+      txx += gx * gx;
+      txy += gx * gy;
+      tyy += gy * gy;
+      ++count;
+    }
+  }
+  const double half_tr = 0.5 * (txx + tyy);
+  const double disc = sqrt(0.25 * (txx - tyy) * (txx - tyy) + txy * txy);
+  const double e1 = half_tr + disc;
+  const double e2 = half_tr - disc > 0.0 ? half_tr - disc : 0.0;
+  const double s1 = sqrt(e1), s2 = sqrt(e2);
+  const double phi = 0.5 * atan2(2.0 * txy, txx - tyy);
+  const double ux = cos(phi), uy = sin(phi);
+  const double sigma = (s1 + A.lambda1) / (s2 + A.lambda1);
+  const double gamma = pow((s1 * s2 + A.lambda2) / (double)count, A.alpha);
+  double la = gamma * sigma, lb = gamma / sigma;
+  la = la < A.lo ? A.lo : (la > A.hi ? A.hi : la);
+  lb = lb < A.lo ? A.lo : (lb > A.hi ? A.hi : lb);
+  float4* out = reinterpret_cast<float4*>(reinterpret_cast<char*>(A.steer) + (int64_t)v * A.steer_pitch);
+  out[u] = make_float4((float)(lb + (la - lb) * ux * ux), (float)((la - lb) * ux * uy),
+                       (float)(lb + (la - lb) * uy * uy), 0.f);
 }
 
 // Persistent form: workgroups take tiles from a device counter until the
@@ -735,6 +1014,74 @@ int launch_fit_src(const LaunchK& K, hipStream_t st) {
 }  // namespace
 
 extern "C" int lpa_k_fit_max_lds_bytes(void) { return kMaxLdsBytes; }
+
+extern "C" int lpa_k_grad(const LaunchK* k, void* stream) {
+  const LaunchK& K = *k;
+  if (K.tile_w * K.tile_h > 256 || (size_t)K.lds_floats2 * sizeof(float2) > (size_t)kMaxLdsBytes) return -1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid(K.tiles_x * K.tiles_y), block(K.tile_w * K.tile_h);
+  const size_t lds = (size_t)K.lds_floats2 * sizeof(float2);
+#define LPA_GRAD(O, S) grad_kernel<O, S><<<grid, block, lds, st>>>(K)
+  if (K.order == 1) {
+    switch (K.src_kind) {
+      case SRC_RAW_U16: LPA_GRAD(1, SRC_RAW_U16); break;
+      case SRC_RAW_F32: LPA_GRAD(1, SRC_RAW_F32); break;
+      case SRC_PLANE_F32: LPA_GRAD(1, SRC_PLANE_F32); break;
+      case SRC_PLANE_F16: LPA_GRAD(1, SRC_PLANE_F16); break;
+      default: return -1;
+    }
+  } else if (K.order == 2) {
+    switch (K.src_kind) {
+      case SRC_RAW_U16: LPA_GRAD(2, SRC_RAW_U16); break;
+      case SRC_RAW_F32: LPA_GRAD(2, SRC_RAW_F32); break;
+      case SRC_PLANE_F32: LPA_GRAD(2, SRC_PLANE_F32); break;
+      case SRC_PLANE_F16: LPA_GRAD(2, SRC_PLANE_F16); break;
+      default: return -1;
+    }
+  } else {
+    return -1;
+  }
+#undef LPA_GRAD
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+extern "C" int lpa_k_steer(const SteerArgs* a, void* stream) {
+  const dim3 grid((a->out_w + 15) / 16, (a->out_h + 15) / 16), block(256);
+  steer_kernel<<<grid, block, 0, static_cast<hipStream_t>(stream)>>>(*a);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+namespace {
+template <int ORDER, bool ICI>
+int launch_steer_src(const LaunchK& K, hipStream_t st) {
+  const dim3 grid(K.tiles_x * K.tiles_y), block(K.tile_w * K.tile_h);
+  const size_t lds = (size_t)K.lds_floats2 * sizeof(float2);
+  switch (K.src_kind) {
+    case SRC_RAW_U16: fit_kernel_steer<ORDER, ICI, SRC_RAW_U16><<<grid, block, lds, st>>>(K); break;
+    case SRC_RAW_F32: fit_kernel_steer<ORDER, ICI, SRC_RAW_F32><<<grid, block, lds, st>>>(K); break;
+    case SRC_PLANE_F32: fit_kernel_steer<ORDER, ICI, SRC_PLANE_F32><<<grid, block, lds, st>>>(K); break;
+    case SRC_PLANE_F16: fit_kernel_steer<ORDER, ICI, SRC_PLANE_F16><<<grid, block, lds, st>>>(K); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+}  // namespace
+
+extern "C" int lpa_k_fit_steered(const LaunchK* k, void* stream) {
+  const LaunchK& K = *k;
+  if (!K.steer || K.tile_w * K.tile_h > 256 || (size_t)K.lds_floats2 * sizeof(float2) > (size_t)kMaxLdsBytes)
+    return -1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (K.order * 2 + (K.need_var ? 1 : 0)) {
+    case 0: return launch_steer_src<0, false>(K, st);
+    case 1: return launch_steer_src<0, true>(K, st);
+    case 2: return launch_steer_src<1, false>(K, st);
+    case 3: return launch_steer_src<1, true>(K, st);
+    case 4: return launch_steer_src<2, false>(K, st);
+    case 5: return launch_steer_src<2, true>(K, st);
+    default: return -1;
+  }
+}
 
 extern "C" int lpa_k_fit(const LaunchK* k, void* stream) {
   const LaunchK& K = *k;

@@ -27,6 +27,7 @@ DTYPE_U16, DTYPE_F32 = 0, 1
 MEM_DEVICE, MEM_HOST = 0, 1
 STORE = {"fused": 0, "fp32": 1, "fp16": 2}
 FLAG_NO_FP64_FALLBACK = 0x1
+MODE = {"lpa": 0, "calpa": 1}
 
 
 class LpaError(RuntimeError):
@@ -55,6 +56,10 @@ class Params(ctypes.Structure):
         ("radii", ctypes.c_double * MAX_SCALES), ("h", ctypes.c_double * MAX_SCALES),
         ("gamma", ctypes.c_double), ("green_ratio", ctypes.c_double), ("storage", ctypes.c_int32),
         ("tau_inv", ctypes.c_double), ("tau_fp64", ctypes.c_double), ("flags", ctypes.c_uint32),
+        ("mode", ctypes.c_int32), ("grad_order", ctypes.c_int32), ("grad_halfwin", ctypes.c_int32),
+        ("pad_", ctypes.c_int32), ("alpha", ctypes.c_double), ("lambda1", ctypes.c_double),
+        ("lambda2", ctypes.c_double), ("grad_radius", ctypes.c_double), ("grad_h", ctypes.c_double),
+        ("max_stretch", ctypes.c_double),
     ]
 
 
@@ -71,6 +76,8 @@ class Output(ctypes.Structure):
         ("rgb", ctypes.c_void_p), ("row_pitch_bytes", ctypes.c_int64),
         ("scale_map", ctypes.c_void_p), ("scale_map_pitch", ctypes.c_int64),
         ("sd_map", ctypes.c_void_p), ("sd_map_pitch", ctypes.c_int64),
+        ("grad_map", ctypes.c_void_p), ("grad_map_pitch", ctypes.c_int64),
+        ("steer_map", ctypes.c_void_p), ("steer_map_pitch", ctypes.c_int64),
     ]
 
 
@@ -209,6 +216,17 @@ def params_struct(p: dict) -> Params:
     q.tau_inv = float(p.get("tau_inv", 0.0))
     q.tau_fp64 = float(p.get("tau_fp64", 0.0))
     q.flags = int(p.get("flags", 0))
+    mode = p.get("mode", "lpa")
+    q.mode = MODE[mode] if isinstance(mode, str) else int(mode)
+    ad = p.get("adapt") or {}
+    q.alpha = float(ad.get("alpha", 0.005))
+    q.lambda1 = float(ad.get("lambda1", 1.0))
+    q.lambda2 = float(ad.get("lambda2", 0.001))
+    q.grad_radius = float(ad.get("grad_radius", 0.0))
+    q.grad_h = float(ad.get("grad_h", 0.0))
+    q.max_stretch = float(ad.get("max_stretch", 0.0))
+    q.grad_order = int(ad.get("grad_order", 0))
+    q.grad_halfwin = int(ad.get("grad_halfwin", 2))
     return q
 
 
@@ -248,7 +266,7 @@ def frame_struct(raws: Sequence, on_device: bool = True) -> Frame:
     return f
 
 
-def output_struct(rgb, scale_map=None, sd_map=None) -> Output:
+def output_struct(rgb, scale_map=None, sd_map=None, grad_map=None, steer_map=None) -> Output:
     o = Output()
     if rgb.dim() != 3 or rgb.shape[2] != 3 or rgb.stride(2) != 1 or rgb.stride(1) != 3:
         raise ValueError("rgb must be (H, W, 3) float32 with interleaved pixels")
@@ -264,6 +282,16 @@ def output_struct(rgb, scale_map=None, sd_map=None) -> Output:
             raise ValueError("sd_map must be (H, W, 3) float32 with interleaved pixels")
         o.sd_map = sd_map.data_ptr()
         o.sd_map_pitch = sd_map.stride(0) * 4
+    if grad_map is not None:
+        if grad_map.dim() != 3 or grad_map.shape[2] != 2 or grad_map.stride(2) != 1 or grad_map.stride(1) != 2:
+            raise ValueError("grad_map must be (H, W, 2) float32 with interleaved pixels")
+        o.grad_map = grad_map.data_ptr()
+        o.grad_map_pitch = grad_map.stride(0) * 4
+    if steer_map is not None:
+        if steer_map.dim() != 3 or steer_map.shape[2] != 4 or steer_map.stride(2) != 1 or steer_map.stride(1) != 4:
+            raise ValueError("steer_map must be (H, W, 4) float32 with interleaved pixels")
+        o.steer_map = steer_map.data_ptr()
+        o.steer_map_pitch = steer_map.stride(0) * 4
     return o
 
 
@@ -350,10 +378,10 @@ class Rig:
             pass
 
     def reconstruct(self, raws, params: dict, out, scale_map=None, stream=None, plain: bool = False,
-                    sd_map=None):
+                    sd_map=None, grad_map=None, steer_map=None):
         fr = frame_struct(raws)
         pr = params_struct(params)
-        ou = output_struct(out, scale_map, sd_map)
+        ou = output_struct(out, scale_map, sd_map, grad_map, steer_map)
         fn = lpa_reconstruct_plain if plain else lpa_reconstruct
         check(fn(self.handle, ctypes.byref(fr), ctypes.byref(pr), ctypes.byref(ou), _stream_handle(stream)))
 
