@@ -215,6 +215,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=160)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-calpa", action="store_true")
     ap.add_argument("--batch-frames", type=int, default=64)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -256,15 +257,16 @@ def main():
     out = torch.empty((params["out_h"], params["out_w"], 3), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def timed(plain: bool, steps: int, warmup: int):
+    def timed(plain: bool, steps: int, warmup: int, prm=None):
+        prm = params if prm is None else prm
         for _ in range(warmup):
-            rig.reconstruct(dev, params, out, plain=plain)
+            rig.reconstruct(dev, prm, out, plain=plain)
         torch.cuda.synchronize()
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         t0 = time.perf_counter()
         evs[0].record(stream)
         for i in range(steps):
-            rig.reconstruct(dev, params, out, plain=plain)
+            rig.reconstruct(dev, prm, out, plain=plain)
             evs[i + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -284,6 +286,19 @@ def main():
         ms_p, _, _ = timed(True, max(3, args.steps // 2), 1)
         plain = {"value": round(n_px / (ms_p * 1e-3) / 1e6, 3), "unit": "Mpixel/s", "ms_per_frame": round(ms_p, 4),
                  "form": "FP32 pre-pass planes + fit, fixed 16x16 tile"}
+    calpa = None
+    if not args.no_calpa:
+        # adaptive anisotropic LPA (Sec. 5.4-5.5): the paper's regularisers and
+        # structure sensitivity, gradient fit at radius 2 (order 1), 5x5
+        # gradient analysis window, eigenvalues of C within [1/4, 4]
+        adapt = {"alpha": 0.005, "lambda1": 1.0, "lambda2": 0.001, "grad_radius": 2.0, "grad_order": 1,
+                 "grad_halfwin": 2, "max_stretch": 2.0}
+        pc = dict(params, mode="calpa", adapt=adapt)
+        print("[bench] timing CALPA (gradient, steering and steered-fit passes)", file=sys.stderr, flush=True)
+        ms_c, _, _ = timed(False, max(3, args.steps // 2), 1, pc)
+        calpa = {"value": round(n_px / (ms_c * 1e-3) / 1e6, 3), "unit": "Mpixel/s", "ms_per_frame": round(ms_c, 4),
+                 "vs_lpa": round(ms_c / ms, 3), "params": adapt,
+                 "form": "G gradient pass + steering pass + steered fit, 16x16 tiles, 3 launches per frame"}
     achieved = flops / (ms * 1e-3) / 1e12
     traffic = measured_traffic("fit_kernel<2,ICI,RAW_U16>")
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
@@ -315,6 +330,7 @@ def main():
                    "form": "fused raw decode + fit, one launch per frame, tuned launch shape",
                    "frames_per_step": 1, "tuned": tuned},
         "plain_fp32": plain,
+        "calpa": calpa,
         "speedup_vs_plain": round(value / plain["value"], 3) if plain else None,
         "roofline": roof,
         "cpu_baseline": cpu,
