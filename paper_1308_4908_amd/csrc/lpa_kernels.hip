@@ -58,6 +58,7 @@ __device__ __forceinline__ void acc_zero(Acc<ORDER, ICI>& a) {
 // vanish at the radius and clamped to zero beyond it.  A sample at or beyond
 // reach2 has exactly zero weight, so the update is skipped there: per lane,
 // and for the whole wave when none of its lanes has the sample in its window.
+// Returns whether the sample belongs to the support (positive weight).
 // A steered window (adaptive anisotropic LPA, Sec. 5.4) replaces |d|^2 by
 // the quadratic form d^T C d of the pixel's steering matrix.
 struct SteerC {
@@ -71,7 +72,7 @@ __device__ __forceinline__ float window_r2(float dx, float dy, float x2, float y
 }
 
 template <int ORDER, bool ICI, bool STEER>
-__device__ __forceinline__ void acc_sample(Acc<ORDER, ICI>& a, float dx, float dy, float f, float iv,
+__device__ __forceinline__ bool acc_sample(Acc<ORDER, ICI>& a, float dx, float dy, float f, float iv,
                                            float e_edge, float reach2, const SteerC& sc) {
   const float x2 = dx * dx, y2 = dy * dy;
   const float r2 = window_r2<STEER>(dx, dy, x2, y2, sc);
@@ -111,7 +112,9 @@ __device__ __forceinline__ void acc_sample(Acc<ORDER, ICI>& a, float dx, float d
 #pragma unroll
       for (int k = 1; k < n_mom<ORDER>(); ++k) a.B[k] = __builtin_fmaf(w2, mono[k], a.B[k]);
     }
+    return w > 0.f;
   }
+  return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -563,10 +566,23 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
       const float reach2 = K.sc[m].reach2[cls];
       Acc<ORDER, ICI> a;
       acc_zero(a);
-      auto accumulate = [&](float dx, float dy, float f, float iv) {
-        acc_sample<ORDER, ICI, STEER>(a, dx, dy, f, iv, eedge, reach2, sc);
-      };
-      walk_support(K, lds, regs, Xj, Yj, c, cls, m, accumulate);
+      // At the first (smallest) radius the support is often smaller than the
+      // number of unknowns; the walk counts it there, which decides those fits
+      // without a second pass.  Elsewhere the count is taken only when needed.
+      int n_first = -1;
+      if (m == 0) {
+        int n = 0;
+        auto accumulate = [&](float dx, float dy, float f, float iv) {
+          n += acc_sample<ORDER, ICI, STEER>(a, dx, dy, f, iv, eedge, reach2, sc) ? 1 : 0;
+        };
+        walk_support(K, lds, regs, Xj, Yj, c, cls, m, accumulate);
+        n_first = n;
+      } else {
+        auto accumulate = [&](float dx, float dy, float f, float iv) {
+          acc_sample<ORDER, ICI, STEER>(a, dx, dy, f, iv, eedge, reach2, sc);
+        };
+        walk_support(K, lds, regs, Xj, Yj, c, cls, m, accumulate);
+      }
 
       // Once every lane of the wave has a valid top-order fit at some radius,
       // the output is that order's ICI result: the lower orders (kept only
@@ -579,19 +595,29 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
         if (K.use_fp64 && fr.ok[2] && fr.rho[2] < K.tau_fp64) refine_order2(a.m, a.b, fr.g[2], fr.y[2]);
       }
       if constexpr (ORDER >= 1) {
-        // Second pass over the samples, taken by the whole wave when any lane
-        // needs it:
-        //  - fits whose FP32 pivot is small are counted and their normal
-        //    matrix re-accumulated in FP64; their validity is decided on its
-        //    FP64 pivots (see pivots_fp64);
-        //  - ill-conditioned valid fits get their variance from positive terms.
-        bool small = false, need_var = false;
+        // Validity where the FP32 pivot cannot certify it (rho < the bound
+        // kPivotCertifiesN) needs the support size N and, if N >= n_o, the
+        // pivots of the normal matrix accumulated in FP64.  A counted support
+        // smaller than n_o decides the fit at once.
+        constexpr int nb_tab[3] = {1, 3, 6};
+        bool small1 = false, small2 = false, need_var = false;
 #pragma unroll
         for (int o = 1; o <= ORDER; ++o) {
-          small = small || ((o == ORDER || lower) && fr.rho[o] < kPivotCertifiesN);
+          bool sm = (o == ORDER || lower) && fr.rho[o] < kPivotCertifiesN;
+          if (sm && n_first >= 0 && n_first < nb_tab[o]) {
+            fr.ok[o] = false;
+            sm = false;
+          }
+          if (o == 1) small1 = sm;
+          else small2 = sm;
           need_var = need_var || (ICI && fr.ok[o] && fr.rho[o] < K.tau_fp64);
         }
-        if (__builtin_amdgcn_ballot_w64(small || need_var) != 0) {
+        // Second pass over the samples, taken by the whole wave when any lane
+        // needs it: FP64 moments (of order 2 only where an order-2 fit needs
+        // them) and, for ill-conditioned fits, the variance from positive terms.
+        const bool pass64 = __builtin_amdgcn_ballot_w64(small1 || small2) != 0;
+        const bool pass64_2 = ORDER >= 2 && __builtin_amdgcn_ballot_w64(small2) != 0;
+        if (pass64 || __builtin_amdgcn_ballot_w64(need_var) != 0) {
           int n = 0;
           double m64[n_mom<ORDER>()];
 #pragma unroll
@@ -606,32 +632,33 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
             if (r2 < reach2) {
               const float kw = fmaxf(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f);
               const float w = kw * iv;
-              n += (w > 0.f) ? 1 : 0;
-              const double wd = w, x = dx, y = dy;
-              const double xx = x * x, xy = x * y, yy = y * y;
-              m64[0] += wd;
-              m64[1] += wd * x;
-              m64[2] += wd * y;
-              m64[3] += wd * xx;
-              m64[4] += wd * xy;
-              m64[5] += wd * yy;
-              if constexpr (ORDER >= 2) {
-                m64[6] += wd * xx * x;
-                m64[7] += wd * xx * y;
-                m64[8] += wd * xy * y;
-                m64[9] += wd * yy * y;
-                m64[10] += wd * xx * xx;
-                m64[11] += wd * xx * xy;
-                m64[12] += wd * xx * yy;
-                m64[13] += wd * xy * yy;
-                m64[14] += wd * yy * yy;
+              if (pass64) {
+                n += (w > 0.f) ? 1 : 0;
+                const double wd = w, x = dx, y = dy;
+                const double xx = x * x, xy = x * y, yy = y * y;
+                m64[0] += wd;
+                m64[1] += wd * x;
+                m64[2] += wd * y;
+                m64[3] += wd * xx;
+                m64[4] += wd * xy;
+                m64[5] += wd * yy;
+                if (pass64_2) {
+                  m64[6] += wd * xx * x;
+                  m64[7] += wd * xx * y;
+                  m64[8] += wd * xy * y;
+                  m64[9] += wd * yy * y;
+                  m64[10] += wd * xx * xx;
+                  m64[11] += wd * xx * xy;
+                  m64[12] += wd * xx * yy;
+                  m64[13] += wd * xy * yy;
+                  m64[14] += wd * yy * yy;
+                }
               }
               if constexpr (ICI) {
                 const float w2 = w * kw;
                 float phi[6] = {1.f, dx, dy, x2, dx * dy, y2};
 #pragma unroll
                 for (int o = 1; o <= ORDER; ++o) {
-                  constexpr int nb_tab[3] = {1, 3, 6};
                   float t = fr.g[o][0];
 #pragma unroll
                   for (int i = 1; i < nb_tab[o]; ++i) t = __builtin_fmaf(fr.g[o][i], phi[i], t);
@@ -641,19 +668,28 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
             }
           };
           walk_support(K, lds, regs, Xj, Yj, c, cls, m, second);
-          double r64[ORDER + 1];
-          pivots_fp64<ORDER>(m64, r64);
-#pragma unroll
-          for (int o = 1; o <= ORDER; ++o) {
-            constexpr int nb_tab[3] = {1, 3, 6};
-            if ((o == ORDER || lower) && fr.rho[o] < kPivotCertifiesN) {
-              bool diag = true;
-#pragma unroll
-              for (int i = 0; i < nb_tab[o]; ++i) diag = diag && m64[aidx(i, i)] > 0.0;
-              fr.rho[o] = diag ? (float)r64[o] : 0.f;
-              fr.ok[o] = diag && r64[o] >= (double)K.tau_inv && n >= nb_tab[o];
+          if (pass64) {
+            double r64[ORDER + 1];
+            if constexpr (ORDER >= 2) {
+              if (pass64_2) pivots_fp64<2>(m64, r64);
+              else pivots_fp64<1>(m64, r64);  // only order-1 fits to decide
+            } else {
+              pivots_fp64<ORDER>(m64, r64);
             }
-            if constexpr (ICI)
+#pragma unroll
+            for (int o = 1; o <= ORDER; ++o) {
+              if ((o == 1) ? small1 : small2) {
+                bool diag = true;
+#pragma unroll
+                for (int i = 0; i < nb_tab[o]; ++i) diag = diag && m64[aidx(i, i)] > 0.0;
+                fr.rho[o] = diag ? (float)r64[o] : 0.f;
+                fr.ok[o] = diag && r64[o] >= (double)K.tau_inv && n >= nb_tab[o];
+              }
+            }
+          }
+          if constexpr (ICI) {
+#pragma unroll
+            for (int o = 1; o <= ORDER; ++o)
               if (fr.rho[o] < K.tau_fp64) fr.v[o] = vs[o];
           }
         }
