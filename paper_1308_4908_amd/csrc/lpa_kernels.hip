@@ -502,11 +502,29 @@ __device__ __forceinline__ void walk_box(const float2* p0, int row_step, int nx,
   }
 }
 
+// Wave-wide bounds on the entries of C^-1 over the wave's steered windows
+// (|.| for the off-diagonal one).  The ellipse d^T C d < r^2 spans
+// r sqrt(a^T C^-1 a) along a direction a, and a^T C^-1 a <= ax^2 pxx +
+// 2 |ax ay| pxy + ay^2 pyy for every lane of the wave.
+struct SteerBox {
+  float pxx, pyy, pxy;
+};
+
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = fmaxf(x, __shfl_xor(x, d, 64));
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+
 // Calls fn(dx, dy, f, iv) for every CFA sample of channel c inside the box of
-// radius index m around (Xj, Yj), over all sensors (scaled offsets).
-template <class Fn>
+// radius index m around (Xj, Yj), over all sensors (scaled offsets).  The
+// box holds the disk of the radius; for steered windows, the wave's ellipses
+// (half-widths from SteerBox, at most the box of the largest stretch, which
+// the staged tile region covers).
+template <bool STEER, class Fn>
 __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds, const Region* regs,
-                                             double Xj, double Yj, int c, int cls, int m, Fn&& fn) {
+                                             double Xj, double Yj, int c, int cls, int m, const SteerBox& sb,
+                                             Fn&& fn) {
   const ScaleK& SC = K.sc[m];
   const double rad = SC.box_radius[cls];
   const float cs = SC.coord_scale[cls];
@@ -516,10 +534,20 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
     // lane position on the sensor and the box half-widths of this radius
     const double px = S.inv[0] * Xj + S.inv[1] * Yj + S.inv[2];
     const double py = S.inv[3] * Xj + S.inv[4] * Yj + S.inv[5];
-    const double wx = rad * S.rownorm[0];
-    const double wy = rad * S.rownorm[1];
-    const int nx = S.nbox[cls][m][0];
-    const int ny = S.nbox[cls][m][1];
+    double wx = rad * S.rownorm[0];
+    double wy = rad * S.rownorm[1];
+    int nx = S.nbox[cls][m][0];
+    int ny = S.nbox[cls][m][1];
+    if constexpr (STEER) {
+      const float ax = (float)S.inv[0], ay = (float)S.inv[1], bx = (float)S.inv[3], by = (float)S.inv[4];
+      const float qx = ax * ax * sb.pxx + 2.f * fabsf(ax * ay) * sb.pxy + ay * ay * sb.pyy;
+      const float qy = bx * bx * sb.pxx + 2.f * fabsf(bx * by) * sb.pxy + by * by * sb.pyy;
+      const float r = (float)SC.radius[cls] * 1.001f;  // margin over rounding of the bound
+      wx = fmin((double)(r * __builtin_amdgcn_sqrtf(qx)), wx);
+      wy = fmin((double)(r * __builtin_amdgcn_sqrtf(qy)), wy);
+      nx = __builtin_amdgcn_readfirstlane(min(nx, max(1, (int)ceil(wx - 1e-9))));
+      ny = __builtin_amdgcn_readfirstlane(min(ny, max(1, (int)ceil(wy - 1e-9))));
+    }
     // step between sub-lattice points (+2 px in x or y), scaled
     const float sax = (float)(2.0 * S.fwd[0] * cs), say = (float)(2.0 * S.fwd[3] * cs);
     const float sbx = (float)(2.0 * S.fwd[1] * cs), sby = (float)(2.0 * S.fwd[4] * cs);
@@ -548,12 +576,19 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
   const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
   const double Yj = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
   SteerC sc = {1.f, 1.f, 0.f};  // lanes outside the grid keep the isotropic window (inside the box)
+  SteerBox sb = {0.f, 0.f, 0.f};
   if constexpr (STEER) {
+    float pxx = 0.f, pyy = 0.f, pxy = 0.f;  // C^-1 of the active lanes
     if (active) {
       const float4 c = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(K.steer) +
                                                        (int64_t)v * K.steer_pitch)[u];
       sc = {c.x, c.z, 2.f * c.y};
+      const float id = 1.f / (c.x * c.z - c.y * c.y);
+      pxx = c.z * id;
+      pyy = c.x * id;
+      pxy = fabsf(c.y * id);
     }
+    sb = {wave_max(pxx), wave_max(pyy), wave_max(pxy)};
   }
   for (int c = 0; c < 3; ++c) {
     const int cls = (c == 1) ? 1 : 0;
@@ -575,13 +610,13 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
         auto accumulate = [&](float dx, float dy, float f, float iv) {
           n += acc_sample<ORDER, ICI, STEER>(a, dx, dy, f, iv, eedge, reach2, sc) ? 1 : 0;
         };
-        walk_support(K, lds, regs, Xj, Yj, c, cls, m, accumulate);
+        walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, accumulate);
         n_first = n;
       } else {
         auto accumulate = [&](float dx, float dy, float f, float iv) {
           acc_sample<ORDER, ICI, STEER>(a, dx, dy, f, iv, eedge, reach2, sc);
         };
-        walk_support(K, lds, regs, Xj, Yj, c, cls, m, accumulate);
+        walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, accumulate);
       }
 
       // Once every lane of the wave has a valid top-order fit at some radius,
@@ -667,7 +702,7 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
               }
             }
           };
-          walk_support(K, lds, regs, Xj, Yj, c, cls, m, second);
+          walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, second);
           if (pass64) {
             double r64[ORDER + 1];
             if constexpr (ORDER >= 2) {
@@ -894,7 +929,7 @@ __global__ void __launch_bounds__(256) grad_kernel(const LaunchK K) {
       }
     }
   };
-  walk_support(K, lds, regs, Xj, Yj, 1, 1, 0, accumulate);
+  walk_support<false>(K, lds, regs, Xj, Yj, 1, 1, 0, SteerBox{}, accumulate);
   double c1x, c1y, rho;
   bool diag_all;
   solve_gradient<ORDER>(m64, b64, c1x, c1y, rho, diag_all);
