@@ -220,7 +220,16 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this size (HBM counter calibration)")
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="only run the FMA issue-rate probe (vector-ALU ceiling without packed FP32)")
     args = ap.parse_args()
+    if args.peak_probe:
+        import subprocess
+
+        probe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1308_4908_amd", "peak_probe")
+        if not os.path.exists(probe):
+            sys.exit(f"{probe} is not built; run __graft_entry__.build() first")
+        sys.exit(subprocess.run([probe]).returncode)
     if args.copy_probe_mib:
         import torch
 

@@ -14,6 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblpa.so")
+PEAK_PROBE = os.path.join(HERE, "peak_probe")  # vector-ALU ceiling measurement (bench.py --peak-probe)
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["lpa_kernels.hip", "lpa_api.cpp", "lpa_batch.cpp", "lpa_serve.cpp", "lpa_tune.cpp"]
 ARCH = os.environ.get("LPA_OFFLOAD_ARCH", "gfx950")
@@ -46,8 +47,13 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    r = subprocess.run(["hipcc", *COMMON, "-o", PEAK_PROBE + ".tmp", os.path.join(CSRC, "peak_probe.hip")],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on peak_probe.hip:\n{r.stderr}")
+    os.replace(PEAK_PROBE + ".tmp", PEAK_PROBE)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PEAK_PROBE}")
     return LIB
 
 
