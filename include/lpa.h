@@ -78,6 +78,22 @@ enum { LPA_STORE_FUSED = 0, LPA_STORE_FP32 = 1, LPA_STORE_FP16 = 2 };
 
 /* lpa_params.flags */
 #define LPA_FLAG_NO_FP64_FALLBACK 0x1u /* never refine ill-conditioned order-2 solves in FP64 */
+/* Pre-computed window weights (Sec. 8: the paper precomputes the weights for
+ * registered sensors at the output resolution).  When every sensor map T_s
+ * and the output map O are translations (linear parts exactly the identity),
+ * the in-window samples of an output pixel, their window weights and their
+ * monomials depend only on the pixel's 2x2 parity; the rig tabulates them
+ * once per parameter class (radii, windows, output translation) in device
+ * memory charged to the context's budget and kept until lpa_destroy_rig.  The
+ * first call of a class builds and uploads its table (blocking).  Same
+ * estimator, validity and ICI rules as the general path; the results agree
+ * with it to rounding (the weights are computed in FP64 and rounded once),
+ * not bit for bit.  Per-frame calls only (lpa_reconstruct,
+ * lpa_reconstruct_plain), isotropic windows only (mode LPA), 16x16 tiles.
+ * Errors: LPA_ERR_UNSUPPORTED for rigs or output maps that are not
+ * translations, CALPA, batches, lpa_submit and lpa_autotune;
+ * LPA_ERR_OOM if the table exceeds the budget. */
+#define LPA_FLAG_PRECOMPUTED_WEIGHTS 0x2u
 
 /* One sensor of a rig (Sec. 3, Sec. 4, Sec. 6). */
 typedef struct {

@@ -463,6 +463,9 @@ static lpa_status calpa_impl(lpa_rig* rig, const lpa_frame* frame, const Resolve
   return st;
 }
 
+// Register budget of the pre-computed-weight kernel (waves per SIMD; 0 = 3).
+constexpr int kStencilOccupancy = 0;
+
 lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
                             const lpa_output* out, void* stream, bool plain) {
   if (!rig) return set_error(LPA_ERR_INVALID_ARG, "rig is NULL");
@@ -476,6 +479,9 @@ lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_para
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return device_error(ctx, e, "hipSetDevice");
   hipStream_t hs = static_cast<hipStream_t>(stream);
+  const bool stencil = (R.p.flags & LPA_FLAG_PRECOMPUTED_WEIGHTS) != 0;
+  if (stencil && R.p.mode != LPA_MODE_LPA)
+    return set_error(LPA_ERR_UNSUPPORTED, "pre-computed weights apply to isotropic windows (mode LPA)");
   if (R.p.mode == LPA_MODE_CALPA) return calpa_impl(rig, frame, R, out, hs, plain);
 
   const int storage = plain ? LPA_STORE_FP32 : R.p.storage;
@@ -501,16 +507,21 @@ lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_para
     }
   }
   TuneChoice tc;
-  if (!plain) {
+  if (!plain && !stencil) {
     tc = ctx->tuner.choose(Tuner::key_of(rig, R, src_kind));
     tw = tc.tile_w;
     th = tc.tile_h;
   }
   LaunchK K;
-  st = plain ? build_launch(rig, R, out, src_kind, srcs, pitches, 16, 16, &K)
-             : build_launch_fit(rig, R, out, src_kind, srcs, pitches, tw, th, &K);
+  // the pre-computed-weight kernel needs one parity class per wave: 16 x 16
+  st = (plain || stencil) ? build_launch(rig, R, out, src_kind, srcs, pitches, 16, 16, &K)
+                          : build_launch_fit(rig, R, out, src_kind, srcs, pitches, tw, th, &K);
   if (st != LPA_OK) return st;
   K.occupancy = tc.occupancy;
+  if (stencil) {
+    if ((st = stencil_table(rig, R, K, &K.stencil)) != LPA_OK) return st;
+    K.occupancy = kStencilOccupancy;
+  }
 
   if (storage != LPA_STORE_FUSED) {
     st = run_prepass(rig, frame, storage == LPA_STORE_FP16, hs, planes, plane_bytes, srcs, pitches);
@@ -520,7 +531,8 @@ lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_para
         K.s[s].pitch = pitches[s];
       }
   }
-  if (st == LPA_OK && lpa_k_fit(&K, hs) != 0) st = device_error(ctx, hipGetLastError(), "fit launch");
+  if (st == LPA_OK && (stencil ? lpa_k_fit_stencil(&K, hs) : lpa_k_fit(&K, hs)) != 0)
+    st = device_error(ctx, hipGetLastError(), "fit launch");
   for (int s = 0; s < rig->n; ++s) free_async(ctx, planes[s], plane_bytes[s], hs);
   return st;
 }
@@ -563,10 +575,9 @@ lpa_status lpa_create_ctx(int device, size_t hbm_budget_bytes, lpa_ctx** out) {
 }
 
 static void rig_free(lpa_rig* rig) {
-  if (rig->d_k) {
-    (void)hipSetDevice(rig->ctx->device);
-    (void)hipFree(rig->d_k);
-  }
+  (void)hipSetDevice(rig->ctx->device);
+  if (rig->d_k) (void)hipFree(rig->d_k);
+  stencil_free(rig);
   delete rig;
 }
 

@@ -42,6 +42,8 @@ lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_f
     lpa_status st = resolve_params(&params[i], &Rs[i]);
     if (st == LPA_OK && Rs[i].p.mode != LPA_MODE_LPA)
       st = set_error(LPA_ERR_UNSUPPORTED, "frame %d: CALPA frames are reconstructed per frame", i);
+    if (st == LPA_OK && (Rs[i].p.flags & LPA_FLAG_PRECOMPUTED_WEIGHTS))
+      st = set_error(LPA_ERR_UNSUPPORTED, "frame %d: pre-computed weights are a per-frame form", i);
     if (st == LPA_OK) st = validate_frame(rigs[i], &frames[i], true);
     if (st == LPA_OK) st = validate_output(&params[i], &outs[i]);
     if (st != LPA_OK) return set_error(st, "frame %d: %s", i, g_last_error);

@@ -145,6 +145,15 @@ struct lpa_rig {
   lpa_sensor_desc desc[LPA_MAX_SENSORS];
   lpa::SensorK k[LPA_MAX_SENSORS];  // host copy of the resident constants
   lpa::SensorK* d_k = nullptr;       // device-resident constants
+  // Pre-computed-weight tables, one per parameter class, built on first use
+  // and kept until the rig is destroyed (a table may be read by queued work).
+  struct Stencil {
+    std::vector<double> key;
+    void* d = nullptr;
+    size_t bytes = 0;
+  };
+  std::mutex stencil_mu;
+  std::vector<Stencil> stencils;
 };
 
 namespace lpa {
@@ -168,6 +177,12 @@ lpa_status alloc_async(lpa_ctx* ctx, size_t bytes, hipStream_t st, void** p, boo
 void free_async(lpa_ctx* ctx, void* p, size_t bytes, hipStream_t st, bool charge = true);
 lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_t st, void** planes,
                        size_t* plane_bytes, const void** srcs, int64_t* pitches, bool charge = true);
+// Pre-computed-weight table of a launch (lpa_stencil.cpp): checks that every
+// sensor map and the output map are translations, then returns the rig's
+// cached device table for the launch's radii and windows, building it on
+// first use.
+lpa_status stencil_table(lpa_rig* rig, const Resolved& R, const LaunchK& K, const StencilTable** out);
+void stencil_free(lpa_rig* rig);
 
 // Runtime pieces owned by a context (scheduler threads, batch tables).
 lpa_status ctx_init_runtime(lpa_ctx* ctx);

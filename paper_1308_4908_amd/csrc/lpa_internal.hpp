@@ -51,6 +51,30 @@ struct ScaleK {
   float e_edge[2];    // exp(-r'^2 / h'): subtracted so the window vanishes at r'
 };
 
+// Pre-computed window weights (rigs whose sensor maps and output map are
+// translations, Sec. 8): the offset from an output pixel to the channel-c
+// samples of a sensor depends only on the pixel's 2x2 parity, so the window
+// weight K and the scaled monomials of every in-window sample are fixed per
+// (channel, parity, radius index, sensor) and tabulated once.
+struct StencilEntry {
+  float a[15];      // K * monomial (Hankel order: 1, x, y, x^2, xy, y^2, x^3, x^2y, xy^2, y^3, x^4, ..., y^4),
+                    // scaled offsets; a[0] is the window weight K
+  int32_t kl;       // sample = output pixel (u, v) + (k, l) in sensor pixels: k in the low 16 bits, l in the
+                    // high 16 bits, both two's complement
+};
+static_assert(sizeof(StencilEntry) == 64, "stencil entry layout: one 64-byte scalar load");
+
+struct StencilSeg {
+  int32_t off, n;   // first entry and entry count
+};
+
+// Device table: the segment index followed by the entries.
+struct StencilTable {
+  StencilSeg seg[3][4][kMaxScales][kMaxSensors];  // [channel][parity: (u & 1) + 2 (v & 1)][radius][sensor]
+  // StencilEntry entries[] follow at entries_offset()
+  static constexpr size_t entries_offset() { return (sizeof(StencilSeg) * 3 * 4 * kMaxScales * kMaxSensors + 255) / 256 * 256; }
+};
+
 struct LaunchK {
   double out_affine[6];
   int32_t out_w, out_h;
@@ -74,6 +98,7 @@ struct LaunchK {
   int64_t steer_pitch;      // bytes
   float* grad;              // gradient pass: per output pixel (df/dX, df/dY), reference-plane units
   int64_t grad_pitch;       // bytes
+  const StencilTable* stencil; // pre-computed-weight fit: the launch's table (device)
   SensorK s[kMaxSensors];
   ScaleK sc[kMaxScales];
 };
@@ -137,6 +162,8 @@ int lpa_k_fit_max_lds_bytes(void);
 int lpa_k_grad(const lpa::LaunchK* k, void* stream);
 // Steering pass over the gradient plane.
 int lpa_k_steer(const lpa::SteerArgs* a, void* stream);
+// Fit with pre-computed window weights read from K.stencil (256-lane tiles).
+int lpa_k_fit_stencil(const lpa::LaunchK* k, void* stream);
 // Fit with per-pixel steered windows read from K.steer.
 int lpa_k_fit_steered(const lpa::LaunchK* k, void* stream);
 // Zero n ints with a small kernel (graph-safe replacement for a memset).

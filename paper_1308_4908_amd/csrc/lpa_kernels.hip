@@ -36,6 +36,11 @@ __host__ __device__ constexpr int bp(int i) { return i == 1 ? 1 : i == 3 ? 2 : i
 __host__ __device__ constexpr int bq(int i) { return i == 2 ? 1 : i == 4 ? 1 : i == 5 ? 2 : 0; }
 __host__ __device__ constexpr int aidx(int i, int j) { return midx(bp(i) + bp(j), bq(i) + bq(j)); }
 
+// Stencil tables seen through the constant address space: uniform reads
+// become scalar loads.
+using ConstEntry = const __attribute__((address_space(4))) StencilEntry;
+using ConstTable = const __attribute__((address_space(4))) StencilTable;
+
 template <int ORDER, bool ICI>
 struct Acc {
   float m[n_mom<ORDER>()];            // sum w * monomial
@@ -570,7 +575,62 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
   }
 }
 
-template <int ORDER, bool ICI, bool STEER>
+// Pre-computed window weights: one tabulated sample of a stencil.  The entry
+// holds K * monomial for every Hankel moment, so A, b and B take one FMA per
+// moment each (w = K iv, w f and K w are formed once per sample).  Returns
+// whether the sample belongs to the support (positive inverse variance).
+template <int ORDER, bool ICI>
+__device__ __forceinline__ bool acc_entry(Acc<ORDER, ICI>& a, const ConstEntry& e, float f, float iv) {
+  const float wf = f * iv;
+#pragma unroll
+  for (int k = 0; k < n_mom<ORDER>(); ++k) a.m[k] = __builtin_fmaf(e.a[k], iv, a.m[k]);
+#pragma unroll
+  for (int k = 0; k < n_basis<ORDER>(); ++k) a.b[k] = __builtin_fmaf(e.a[k], wf, a.b[k]);
+  if constexpr (ICI) {
+    const float wk = e.a[0] * iv;  // a[0] = K
+#pragma unroll
+    for (int k = 0; k < n_mom<ORDER>(); ++k) a.B[k] = __builtin_fmaf(e.a[k], wk, a.B[k]);
+  }
+  return iv > 0.f;
+}
+
+// Calls fn(entry, f, iv) for every tabulated sample of channel c, radius index
+// m, for the wave's output-pixel parity `par` (uniform: a 256-lane tile puts
+// one parity class in each wave).  Entries are read through the constant
+// address space with uniform addresses: scalar loads, no vector registers.
+template <class Fn>
+__device__ __forceinline__ void walk_stencil(const LaunchK& K, const float2* lds, const Region* regs, int u, int v,
+                                             int c, int par, int m, Fn&& fn) {
+  // a C-style cast is the address-space cast (generic -> constant)
+  const ConstTable* T = (const ConstTable*)K.stencil;
+  const ConstEntry* E = (const ConstEntry*)((const __attribute__((address_space(4))) char*)T +
+                                            StencilTable::entries_offset());
+  for (int s = 0; s < K.n_sensors; ++s) {
+    const int off = T->seg[c][par][m][s].off, n = T->seg[c][par][m][s].n;
+    const Region R = regs[s];
+    const int rw = __builtin_amdgcn_readfirstlane(R.w);
+    // LDS index of sensor pixel (u, v) of the staged region (it may lie
+    // outside the region; every tabulated sample lies inside it)
+    const int base = K.s[s].lds_off + (v - R.y0) * rw + (u - R.x0);
+    // pairs: one wait covers both entries' scalar loads, one both LDS reads
+    int i = 0;
+    for (; i + 1 < n; i += 2) {
+      const ConstEntry& e0 = E[off + i];
+      const ConstEntry& e1 = E[off + i + 1];
+      const float2 f0 = lds[base + (e0.kl >> 16) * rw + (int)(short)e0.kl];
+      const float2 f1 = lds[base + (e1.kl >> 16) * rw + (int)(short)e1.kl];
+      fn(e0, f0.x, f0.y);
+      fn(e1, f1.x, f1.y);
+    }
+    if (i < n) {
+      const ConstEntry& e = E[off + i];
+      const float2 fi = lds[base + (e.kl >> 16) * rw + (int)(short)e.kl];
+      fn(e, fi.x, fi.y);
+    }
+  }
+}
+
+template <int ORDER, bool ICI, bool STEER, bool STENCIL = false>
 __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, const Region* regs,
                                           int u, int v, bool active) {
   const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
@@ -590,6 +650,7 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
     }
     sb = {wave_max(pxx), wave_max(pyy), wave_max(pxy)};
   }
+  const int par = __builtin_amdgcn_readfirstlane((u & 1) + 2 * (v & 1));
   for (int c = 0; c < 3; ++c) {
     const int cls = (c == 1) ? 1 : 0;
     IciState st[ORDER + 1];
@@ -605,7 +666,19 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
       // number of unknowns; the walk counts it there, which decides those fits
       // without a second pass.  Elsewhere the count is taken only when needed.
       int n_first = -1;
-      if (m == 0) {
+      if constexpr (STENCIL) {
+        if (m == 0) {
+          int n = 0;
+          auto accumulate = [&](const ConstEntry& e, float f, float iv) {
+            n += acc_entry<ORDER, ICI>(a, e, f, iv) ? 1 : 0;
+          };
+          walk_stencil(K, lds, regs, u, v, c, par, m, accumulate);
+          n_first = n;
+        } else {
+          auto accumulate = [&](const ConstEntry& e, float f, float iv) { acc_entry<ORDER, ICI>(a, e, f, iv); };
+          walk_stencil(K, lds, regs, u, v, c, par, m, accumulate);
+        }
+      } else if (m == 0) {
         int n = 0;
         auto accumulate = [&](float dx, float dy, float f, float iv) {
           n += acc_sample<ORDER, ICI, STEER>(a, dx, dy, f, iv, eedge, reach2, sc) ? 1 : 0;
@@ -677,16 +750,18 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
                 m64[3] += wd * xx;
                 m64[4] += wd * xy;
                 m64[5] += wd * yy;
-                if (pass64_2) {
-                  m64[6] += wd * xx * x;
-                  m64[7] += wd * xx * y;
-                  m64[8] += wd * xy * y;
-                  m64[9] += wd * yy * y;
-                  m64[10] += wd * xx * xx;
-                  m64[11] += wd * xx * xy;
-                  m64[12] += wd * xx * yy;
-                  m64[13] += wd * xy * yy;
-                  m64[14] += wd * yy * yy;
+                if constexpr (ORDER >= 2) {
+                  if (pass64_2) {
+                    m64[6] += wd * xx * x;
+                    m64[7] += wd * xx * y;
+                    m64[8] += wd * xy * y;
+                    m64[9] += wd * yy * y;
+                    m64[10] += wd * xx * xx;
+                    m64[11] += wd * xx * xy;
+                    m64[12] += wd * xx * yy;
+                    m64[13] += wd * xy * yy;
+                    m64[14] += wd * yy * yy;
+                  }
                 }
               }
               if constexpr (ICI) {
@@ -702,7 +777,37 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
               }
             }
           };
-          walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, second);
+          if constexpr (STENCIL) {
+            // the same sums over tabulated samples: K * monomial comes from the
+            // entry, and (g . phi)^2 K w = (g . (K phi))^2 iv
+            auto second_e = [&](const ConstEntry& e, float f, float iv) {
+              (void)f;
+              if (pass64) {
+                n += (iv > 0.f) ? 1 : 0;
+                const double ivd = iv;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) m64[k] += (double)e.a[k] * ivd;
+                if constexpr (ORDER >= 2) {
+                  if (pass64_2) {
+#pragma unroll
+                    for (int k = 6; k < 15; ++k) m64[k] += (double)e.a[k] * ivd;
+                  }
+                }
+              }
+              if constexpr (ICI) {
+#pragma unroll
+                for (int o = 1; o <= ORDER; ++o) {
+                  float t = fr.g[o][0] * e.a[0];
+#pragma unroll
+                  for (int i = 1; i < nb_tab[o]; ++i) t = __builtin_fmaf(fr.g[o][i], e.a[i], t);
+                  vs[o] = __builtin_fmaf(t * t, iv, vs[o]);
+                }
+              }
+            };
+            walk_stencil(K, lds, regs, u, v, c, par, m, second_e);
+          } else {
+            walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, second);
+          }
           if (pass64) {
             double r64[ORDER + 1];
             if constexpr (ORDER >= 2) {
@@ -758,7 +863,7 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
   }
 }
 
-template <int ORDER, bool ICI, int SRC, bool STEER = false>
+template <int ORDER, bool ICI, int SRC, bool STEER = false, bool STENCIL = false>
 __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2* lds, Region* regs) {
   const int tx = tile % K.tiles_x;
   const int ty = tile / K.tiles_x;
@@ -772,7 +877,7 @@ __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2*
   const int u = u0 + du, v = v0 + dv;
   const bool active = (u < K.out_w) && (v < K.out_h);
   // inactive lanes of a ragged tile compute at their nominal pixel (staged)
-  fit_pixel<ORDER, ICI, STEER>(K, lds, regs, u, v, active);
+  fit_pixel<ORDER, ICI, STEER, STENCIL>(K, lds, regs, u, v, active);
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup i runs on
@@ -815,6 +920,25 @@ fit_kernel_steer(const LaunchK K) {
   extern __shared__ float2 lds[];
   __shared__ Region regs[kMaxSensors];
   process_tile<ORDER, ICI, SRC, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
+}
+
+// Fit with pre-computed window weights (translation-only rigs, 256-lane
+// tiles): the per-sample work is the moment FMAs alone.  Two register
+// budgets, 3 and 4 waves per SIMD (the launch descriptor's occupancy picks).
+template <int ORDER, bool ICI, int SRC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+fit_kernel_stencil(const LaunchK K) {
+  extern __shared__ float2 lds[];
+  __shared__ Region regs[kMaxSensors];
+  process_tile<ORDER, ICI, SRC, false, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
+}
+
+template <int ORDER, bool ICI, int SRC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+fit_kernel_stencil_occ4(const LaunchK K) {
+  extern __shared__ float2 lds[];
+  __shared__ Region regs[kMaxSensors];
+  process_tile<ORDER, ICI, SRC, false, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
 }
 
 // Full coefficient vector of one fit in FP64: LDL^T of A (as in solve_fits),
@@ -1150,6 +1274,45 @@ extern "C" int lpa_k_fit_steered(const LaunchK* k, void* stream) {
     case 3: return launch_steer_src<1, true>(K, st);
     case 4: return launch_steer_src<2, false>(K, st);
     case 5: return launch_steer_src<2, true>(K, st);
+    default: return -1;
+  }
+}
+
+namespace {
+template <int ORDER, bool ICI, int SRC>
+void launch_stencil_one(const LaunchK& K, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+  if (K.occupancy == 4) fit_kernel_stencil_occ4<ORDER, ICI, SRC><<<grid, block, lds, st>>>(K);
+  else fit_kernel_stencil<ORDER, ICI, SRC><<<grid, block, lds, st>>>(K);
+}
+
+template <int ORDER, bool ICI>
+int launch_stencil_src(const LaunchK& K, hipStream_t st) {
+  const dim3 grid(K.tiles_x * K.tiles_y), block(K.tile_w * K.tile_h);
+  const size_t lds = (size_t)K.lds_floats2 * sizeof(float2);
+  switch (K.src_kind) {
+    case SRC_RAW_U16: launch_stencil_one<ORDER, ICI, SRC_RAW_U16>(K, grid, block, lds, st); break;
+    case SRC_RAW_F32: launch_stencil_one<ORDER, ICI, SRC_RAW_F32>(K, grid, block, lds, st); break;
+    case SRC_PLANE_F32: launch_stencil_one<ORDER, ICI, SRC_PLANE_F32>(K, grid, block, lds, st); break;
+    case SRC_PLANE_F16: launch_stencil_one<ORDER, ICI, SRC_PLANE_F16>(K, grid, block, lds, st); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+}  // namespace
+
+extern "C" int lpa_k_fit_stencil(const LaunchK* k, void* stream) {
+  const LaunchK& K = *k;
+  // one parity class per wave needs 256-lane tiles
+  if (!K.stencil || K.tile_w * K.tile_h != 256 || (size_t)K.lds_floats2 * sizeof(float2) > (size_t)kMaxLdsBytes)
+    return -1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (K.order * 2 + (K.need_var ? 1 : 0)) {
+    case 0: return launch_stencil_src<0, false>(K, st);
+    case 1: return launch_stencil_src<0, true>(K, st);
+    case 2: return launch_stencil_src<1, false>(K, st);
+    case 3: return launch_stencil_src<1, true>(K, st);
+    case 4: return launch_stencil_src<2, false>(K, st);
+    case 5: return launch_stencil_src<2, true>(K, st);
     default: return -1;
   }
 }

@@ -321,6 +321,8 @@ lpa_status lpa_submit(lpa_rig* rig, const lpa_frame* frame, const lpa_params* pa
     if ((st = resolve_params(params, &R)) != LPA_OK) return st;
     if (R.p.mode != LPA_MODE_LPA)
       return set_error(LPA_ERR_UNSUPPORTED, "CALPA frames are reconstructed per frame (lpa_reconstruct)");
+    if (R.p.flags & LPA_FLAG_PRECOMPUTED_WEIGHTS)
+      return set_error(LPA_ERR_UNSUPPORTED, "pre-computed weights are a per-frame form (lpa_reconstruct)");
     if ((st = validate_frame(rig, frame, false)) != LPA_OK) return st;
     if ((st = validate_output(params, out)) != LPA_OK) return st;
     Scheduler* s = ctx->sched;

@@ -53,6 +53,8 @@ lpa_status lpa_autotune(lpa_rig* rig, const lpa_frame* frame, const lpa_params* 
     if ((st = resolve_params(params, &R)) != LPA_OK) return st;
     if (R.p.mode != LPA_MODE_LPA)
       return set_error(LPA_ERR_UNSUPPORTED, "CALPA frames are reconstructed per frame (lpa_reconstruct)");
+    if (R.p.flags & LPA_FLAG_PRECOMPUTED_WEIGHTS)
+      return set_error(LPA_ERR_UNSUPPORTED, "pre-computed weights use a fixed 16x16 launch (not tuned)");
     if ((st = validate_frame(rig, frame, true)) != LPA_OK) return st;
     if ((st = validate_output(params, out)) != LPA_OK) return st;
     if (reps < 1 || reps > 1000) return set_error(LPA_ERR_INVALID_ARG, "reps %d outside 1..1000", reps);

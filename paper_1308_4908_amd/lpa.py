@@ -27,6 +27,7 @@ DTYPE_U16, DTYPE_F32 = 0, 1
 MEM_DEVICE, MEM_HOST = 0, 1
 STORE = {"fused": 0, "fp32": 1, "fp16": 2}
 FLAG_NO_FP64_FALLBACK = 0x1
+FLAG_PRECOMPUTED_WEIGHTS = 0x2
 MODE = {"lpa": 0, "calpa": 1}
 
 
@@ -215,7 +216,7 @@ def params_struct(p: dict) -> Params:
     q.storage = STORE[st] if isinstance(st, str) else int(st)
     q.tau_inv = float(p.get("tau_inv", 0.0))
     q.tau_fp64 = float(p.get("tau_fp64", 0.0))
-    q.flags = int(p.get("flags", 0))
+    q.flags = int(p.get("flags", 0)) | (FLAG_PRECOMPUTED_WEIGHTS if p.get("precomputed_weights") else 0)
     mode = p.get("mode", "lpa")
     q.mode = MODE[mode] if isinstance(mode, str) else int(mode)
     ad = p.get("adapt") or {}

@@ -7,6 +7,8 @@ full       4 x 2048^2 raw, exposures 1, 1/4, 1/16, 1/64, +-2 px / +-0.3 deg,
 resampled  the small rig, output 4096^2 with X = (u + 1/2)/16 - 1/2, FP16 storage.
 batch      64 frames of mixed size / sensor count / order (see batch_frames).
 served     8 cameras, fixed rig per camera (see camera_rigs).
+aligned    the full workload's rig without rotation (translation-only sensor
+           maps), for the pre-computed-weight form.
 
 Noise for all: gain 0.5 DN/e-, readout sigma 3 DN, black 64, saturation 4095,
 12-bit RGGB.  These stand in for the paper's four-sensor KAI-04050 rig
@@ -42,6 +44,20 @@ def small_rig(seed=1000, size=256):
 
 def full_rig(seed=2000, size=2048):
     return _rig.random_rig(4, size, size, [1.0, 1.0 / 4, 1.0 / 16, 1.0 / 64], 2.0, 0.3, seed, **NOISE)
+
+
+def aligned_rig(seed=2000, size=2048, n_sensors=4):
+    """The full rig's exposures and translations without rotation (registered
+    sensors, e.g. behind a beam splitter): every sensor map is a translation."""
+    return _rig.random_rig(n_sensors, size, size, [1.0, 1.0 / 4, 1.0 / 16, 1.0 / 64][:n_sensors], 2.0, 0.0, seed,
+                           **NOISE)
+
+
+def aligned(seed=2000, size=2048, storage="fused"):
+    """(sensors, scene, params) of the 4-sensor order-2 ICI workload on the aligned rig."""
+    sensors = aligned_rig(seed, size)
+    scene = EdgeScene(size, size, seed)
+    return sensors, scene, lpa_params(size, size, 2, [1.0, 2.0, 3.0, 4.0], storage=storage)
 
 
 def small(seed=1000, size=256):
