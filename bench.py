@@ -42,6 +42,11 @@ RADII = [1.0, 2.0, 3.0, 4.0]
 FLOP_PER_SAMPLE = 19          # transform 8, |d|^2 3, quadratic basis 3, radiance 1, inverse variance 4
 FLOP_PER_SAMPLE_SCALE = 111   # window 3, weight 1, basis products 5, A 42, b 12, ICI B 48
 FLOP_PER_SOLVE = 294          # 6x6 equilibrated Cholesky + C0 + variance
+# With pre-computed window weights the window, weight and basis products come
+# from the tables: per sample the radiance and inverse variance (5), per
+# sample-radius update w f and K w (2) and the 36 moment FMAs (72).
+FLOP_PER_SAMPLE_STENCIL = 5
+FLOP_PER_SAMPLE_SCALE_STENCIL = 74
 
 
 def algorithmic_flops(raws, sensors, n_pixels: int) -> float:
@@ -216,6 +221,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-calpa", action="store_true")
+    ap.add_argument("--no-precomputed", action="store_true")
     ap.add_argument("--batch-frames", type=int, default=64)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -266,16 +272,18 @@ def main():
     out = torch.empty((params["out_h"], params["out_w"], 3), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def timed(plain: bool, steps: int, warmup: int, prm=None):
+    def timed(plain: bool, steps: int, warmup: int, prm=None, rig_=None, dev_=None):
         prm = params if prm is None else prm
+        rig_ = rig if rig_ is None else rig_
+        dev_ = dev if dev_ is None else dev_
         for _ in range(warmup):
-            rig.reconstruct(dev, prm, out, plain=plain)
+            rig_.reconstruct(dev_, prm, out, plain=plain)
         torch.cuda.synchronize()
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         t0 = time.perf_counter()
         evs[0].record(stream)
         for i in range(steps):
-            rig.reconstruct(dev, prm, out, plain=plain)
+            rig_.reconstruct(dev_, prm, out, plain=plain)
             evs[i + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -308,6 +316,33 @@ def main():
         calpa = {"value": round(n_px / (ms_c * 1e-3) / 1e6, 3), "unit": "Mpixel/s", "ms_per_frame": round(ms_c, 4),
                  "vs_lpa": round(ms_c / ms, 3), "params": adapt,
                  "form": "G gradient pass + steering pass + steered fit, 16x16 tiles, 3 launches per frame"}
+    pre = None
+    if not args.no_precomputed:
+        # the paper's fast path for registered sensors (Sec. 8): the same
+        # workload on the rig without rotation, general kernel vs pre-computed
+        # window weights
+        print("[bench] generating the aligned (translation-only) frame", file=sys.stderr, flush=True)
+        a_sensors, a_scene, a_params = configs.aligned(size=size)
+        a_raws = configs.capture_all(a_scene, a_sensors, 2000)
+        a_rig = Rig(ctx, a_sensors)
+        a_dev = [torch.from_numpy(r).cuda() for r in a_raws]
+        print("[bench] timing pre-computed weights vs the general kernel", file=sys.stderr, flush=True)
+        ms_g, _, _ = timed(False, max(3, args.steps // 2), 1, a_params, a_rig, a_dev)
+        ms_s, _, _ = timed(False, max(3, args.steps // 2), 2, dict(a_params, precomputed_weights=True), a_rig, a_dev)
+        _, _, a_samples, a_updates = algorithmic_flops(a_raws, a_sensors, n_px)
+        s_flop_px = (FLOP_PER_SAMPLE_STENCIL * a_samples + FLOP_PER_SAMPLE_SCALE_STENCIL * a_updates +
+                     FLOP_PER_SOLVE * 3 * len(RADII))
+        s_ach = s_flop_px * n_px / (ms_s * 1e-3) / 1e12
+        pre = {"workload": f"aligned rig: {len(a_sensors)} x {size}x{size} raw uint16, translation-only sensor maps, "
+                           "same exposures, noise and LPA parameters", "value": round(n_px / (ms_s * 1e-3) / 1e6, 3),
+               "unit": "Mpixel/s", "ms_per_frame": round(ms_s, 4), "general_kernel_ms_same_frame": round(ms_g, 4),
+               "speedup_vs_general": round(ms_g / ms_s, 3),
+               "form": "fit_kernel_stencil (per-parity tables of K x monomials, scalar loads), 16x16 tiles",
+               "roofline": {"bound": "alu", "achieved": round(s_ach, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                            "unit": "TFLOP/s", "frac": round(s_ach / PEAK_FP32_VECTOR_TFLOPS, 4),
+                            "flop_per_pixel": round(s_flop_px, 1)}}
+        a_rig.close()
+        del a_dev
     achieved = flops / (ms * 1e-3) / 1e12
     traffic = measured_traffic("fit_kernel<2,ICI,RAW_U16>")
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
@@ -340,6 +375,7 @@ def main():
                    "frames_per_step": 1, "tuned": tuned},
         "plain_fp32": plain,
         "calpa": calpa,
+        "precomputed_weights": pre,
         "speedup_vs_plain": round(value / plain["value"], 3) if plain else None,
         "roofline": roof,
         "cpu_baseline": cpu,

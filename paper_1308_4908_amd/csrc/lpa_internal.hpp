@@ -59,8 +59,8 @@ struct ScaleK {
 struct StencilEntry {
   float a[15];      // K * monomial (Hankel order: 1, x, y, x^2, xy, y^2, x^3, x^2y, xy^2, y^3, x^4, ..., y^4),
                     // scaled offsets; a[0] is the window weight K
-  int32_t kl;       // sample = output pixel (u, v) + (k, l) in sensor pixels: k in the low 16 bits, l in the
-                    // high 16 bits, both two's complement
+  int32_t delta;    // LDS offset of the sample from output pixel (u, v)'s own position, l * reg_w + k for
+                    // sample = (u + k, v + l) in sensor pixels (tiles staged with row pitch reg_w)
 };
 static_assert(sizeof(StencilEntry) == 64, "stencil entry layout: one 64-byte scalar load");
 

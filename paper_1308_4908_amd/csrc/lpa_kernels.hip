@@ -411,6 +411,9 @@ struct Region {
   int x0, y0, w, h;
 };
 
+// FULL_PITCH: rows are reg_w samples apart in every tile (pre-computed-weight
+// tables hold LDS offsets l * reg_w + k).
+template <bool FULL_PITCH = false>
 __device__ __forceinline__ Region tile_region(const LaunchK& K, const SensorK& S, int u0, int v0) {
   double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300;
 #pragma unroll
@@ -429,17 +432,17 @@ __device__ __forceinline__ Region tile_region(const LaunchK& K, const SensorK& S
   Region r;
   r.x0 = (int)floor(mnx - S.wmax[0]) - 1;
   r.y0 = (int)floor(mny - S.wmax[1]) - 1;
-  r.w = min((int)ceil(mxx + S.wmax[0]) + 3 - r.x0 + 1, S.reg_w);
+  r.w = FULL_PITCH ? S.reg_w : min((int)ceil(mxx + S.wmax[0]) + 3 - r.x0 + 1, S.reg_w);
   r.h = min((int)ceil(mxy + S.wmax[1]) + 3 - r.y0 + 1, S.reg_h);
   return r;
 }
 
-template <int SRC>
+template <int SRC, bool FULL_PITCH = false>
 __device__ __forceinline__ void stage_tile(const LaunchK& K, int u0, int v0, float2* lds, Region* regs,
                                            int tid, int nthreads) {
   for (int s = 0; s < K.n_sensors; ++s) {
     const SensorK& S = K.s[s];
-    const Region r = tile_region(K, S, u0, v0);
+    const Region r = tile_region<FULL_PITCH>(K, S, u0, v0);
     regs[s] = r;
     float2* dst = lds + S.lds_off;
     const int total = r.w * r.h;
@@ -608,23 +611,22 @@ __device__ __forceinline__ void walk_stencil(const LaunchK& K, const float2* lds
   for (int s = 0; s < K.n_sensors; ++s) {
     const int off = T->seg[c][par][m][s].off, n = T->seg[c][par][m][s].n;
     const Region R = regs[s];
-    const int rw = __builtin_amdgcn_readfirstlane(R.w);
-    // LDS index of sensor pixel (u, v) of the staged region (it may lie
-    // outside the region; every tabulated sample lies inside it)
-    const int base = K.s[s].lds_off + (v - R.y0) * rw + (u - R.x0);
+    // LDS index of sensor pixel (u, v) in the staged region (row pitch reg_w;
+    // it may lie outside the region, every tabulated sample lies inside it)
+    const int base = K.s[s].lds_off + (v - R.y0) * K.s[s].reg_w + (u - R.x0);
     // pairs: one wait covers both entries' scalar loads, one both LDS reads
     int i = 0;
     for (; i + 1 < n; i += 2) {
       const ConstEntry& e0 = E[off + i];
       const ConstEntry& e1 = E[off + i + 1];
-      const float2 f0 = lds[base + (e0.kl >> 16) * rw + (int)(short)e0.kl];
-      const float2 f1 = lds[base + (e1.kl >> 16) * rw + (int)(short)e1.kl];
+      const float2 f0 = lds[base + e0.delta];
+      const float2 f1 = lds[base + e1.delta];
       fn(e0, f0.x, f0.y);
       fn(e1, f1.x, f1.y);
     }
     if (i < n) {
       const ConstEntry& e = E[off + i];
-      const float2 fi = lds[base + (e.kl >> 16) * rw + (int)(short)e.kl];
+      const float2 fi = lds[base + e.delta];
       fn(e, fi.x, fi.y);
     }
   }
@@ -870,7 +872,7 @@ __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2*
   const int u0 = tx * K.tile_w, v0 = ty * K.tile_h;
   const int tid = threadIdx.x;
   const int nthreads = K.tile_w * K.tile_h;
-  stage_tile<SRC>(K, u0, v0, lds, regs, tid, nthreads);
+  stage_tile<SRC, STENCIL>(K, u0, v0, lds, regs, tid, nthreads);
   __syncthreads();
   int du, dv;
   lane_pixel(tid, K.tile_w, K.tile_h, &du, &dv);

@@ -10,6 +10,9 @@
 // every pixel of one parity: they are tabulated here, in FP64 and rounded once
 // to FP32, per (channel, parity, radius, sensor).
 //
+// Each entry holds its sample's LDS offset from the output pixel's own
+// position for the launch's row pitch (reg_w, part of the table's key).
+//
 // Support and weight follow the definition the kernels and the oracle share:
 // the disc |d| < r' with K = exp(-|d|^2 / h') - exp(-r'^2 / h') > 0.  The
 // monomials are taken in the launch's scaled coordinates (s d, s the radius'
@@ -44,6 +47,7 @@ lpa_status stencil_table(lpa_rig* rig, const Resolved& R, const LaunchK& K, cons
   // The table depends on the output map's translation, the radii and the
   // windows (through K.sc: radius, coordinate scale per channel class).
   std::vector<double> key = {O[2], O[5], (double)p.n_scales};
+  for (int s = 0; s < rig->n; ++s) key.push_back((double)K.s[s].reg_w);
   for (int m = 0; m < p.n_scales; ++m)
     for (int cls = 0; cls < 2; ++cls) {
       key.push_back(K.sc[m].radius[cls]);
@@ -74,6 +78,7 @@ lpa_status stencil_table(lpa_rig* rig, const Resolved& R, const LaunchK& K, cons
         const double k_edge = std::exp(-r * r / h);
         for (int s = 0; s < rig->n; ++s) {
           const SensorK& S = rig->k[s];
+          const SensorK& S_l = K.s[s];  // the launch's LDS region bound (row pitch)
           const double tx = rig->desc[s].affine[2] - O[2], ty = rig->desc[s].affine[5] - O[5];
           const int off = (int)ents.size();
           for (int q = 0; q < S.sub_n[c]; ++q) {
@@ -81,9 +86,9 @@ lpa_status stencil_table(lpa_rig* rig, const Resolved& R, const LaunchK& K, cons
             const int kp = ((S.sub_ox[c][q] - pu) % 2 + 2) % 2, lp = ((S.sub_oy[c][q] - pv) % 2 + 2) % 2;
             // in-window offsets: |k + tx| < r, |l + ty| < r
             const int k0 = (int)std::floor(-tx - r) - 1, k1 = (int)std::ceil(-tx + r) + 1;
+            if (!(std::fabs(tx) < 1e6 && std::fabs(ty) < 1e6))
+              return set_error(LPA_ERR_UNSUPPORTED, "sensor %d is offset by more than 1e6 px from the output grid", s);
             const int l0 = (int)std::floor(-ty - r) - 1, l1 = (int)std::ceil(-ty + r) + 1;
-            if (k0 < -32000 || k1 > 32000 || l0 < -32000 || l1 > 32000)
-              return set_error(LPA_ERR_UNSUPPORTED, "sensor %d is offset by more than 32000 px from the output grid", s);
             for (int l = l0; l <= l1; ++l) {
               if (((l - lp) & 1) != 0) continue;
               for (int k = k0; k <= k1; ++k) {
@@ -100,7 +105,7 @@ lpa_status stencil_table(lpa_rig* rig, const Resolved& R, const LaunchK& K, cons
                 double yp[5] = {1, y, y * y, y * y * y, y * y * y * y};
                 for (int pp = 0; pp <= 4; ++pp)
                   for (int qq = 0; pp + qq <= 4; ++qq) e.a[hankel(pp, qq)] = (float)(w * xp[pp] * yp[qq]);
-                e.kl = (int32_t)(((uint32_t)(uint16_t)(int16_t)l << 16) | (uint16_t)(int16_t)k);
+                e.delta = l * S_l.reg_w + k;
                 ents.push_back(e);
               }
             }

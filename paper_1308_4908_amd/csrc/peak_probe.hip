@@ -13,6 +13,9 @@ namespace {
 
 constexpr int kBlocks = 8192, kThreads = 256, kIters = 4096;
 
+__device__ __forceinline__ float fma_of(float x, float a, float b) { return __builtin_fmaf(x, a, b); }
+__device__ __forceinline__ double fma_of(double x, double a, double b) { return __builtin_fma(x, a, b); }
+
 template <typename T, int NCH>
 __global__ void __launch_bounds__(kThreads) fma_chains(T* out, int iters, T a, T b) {
   T x[NCH];
@@ -20,7 +23,7 @@ __global__ void __launch_bounds__(kThreads) fma_chains(T* out, int iters, T a, T
   for (int i = 0; i < NCH; ++i) x[i] = (T)threadIdx.x * (T)1e-3 + (T)i;
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
-    for (int i = 0; i < NCH; ++i) x[i] = __builtin_fma(x[i], a, b);
+    for (int i = 0; i < NCH; ++i) x[i] = fma_of(x[i], a, b);
   }
   T s = 0;
 #pragma unroll
