@@ -41,6 +41,11 @@ class _Sensor(ctypes.Structure):
         ("read_sigma", ctypes.c_double),
         ("black_level", ctypes.c_double),
         ("saturation", ctypes.c_double),
+        ("bias", ctypes.c_void_p),
+        ("prnu", ctypes.c_void_p),
+        ("read_var", ctypes.c_void_p),
+        ("sat", ctypes.c_void_p),
+        ("defect", ctypes.c_void_p),
     ]
 
 
@@ -153,6 +158,11 @@ def _load():
             ctypes.POINTER(_Sensor), ctypes.c_double, ctypes.POINTER(ctypes.c_double),
             ctypes.POINTER(ctypes.c_double),
         ]
+        lib.orc_sample_radiance_at.restype = ctypes.c_int
+        lib.orc_sample_radiance_at.argtypes = [
+            ctypes.POINTER(_Sensor), ctypes.c_int64, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+            ctypes.POINTER(ctypes.c_double),
+        ]
         lib.orc_cfa_channel.restype = ctypes.c_int
         lib.orc_cfa_channel.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         lib.orc_ici_select.restype = ctypes.c_int
@@ -177,6 +187,19 @@ def _sensor_struct(d: dict) -> _Sensor:
     s.read_sigma = float(d["read_sigma"])
     s.black_level = float(d["black_level"])
     s.saturation = float(d["saturation"])
+    # optional per-pixel calibration frames (kept alive on the struct)
+    keep = []
+    calib = d.get("calib") or {}
+    for name in ("bias", "prnu", "read_var", "sat"):
+        if calib.get(name) is not None:
+            a = np.ascontiguousarray(np.asarray(calib[name], dtype=np.float64).reshape(s.height, s.width))
+            keep.append(a)
+            setattr(s, name, a.ctypes.data)
+    if calib.get("defect") is not None:
+        a = np.ascontiguousarray(np.asarray(calib["defect"], dtype=np.uint8).reshape(s.height, s.width))
+        keep.append(a)
+        s.defect = a.ctypes.data
+    s._keep = keep
     return s
 
 
@@ -212,7 +235,8 @@ def reconstruct(sensors, raws, params, pixels=None, want_fits=False, exhaustive=
     """
     lib = _load()
     ns = len(sensors)
-    sens = (_Sensor * ns)(*[_sensor_struct(d) for d in sensors])
+    structs = [_sensor_struct(d) for d in sensors]  # hold the calibration frames during the call
+    sens = (_Sensor * ns)(*structs)
     planes = [np.ascontiguousarray(np.asarray(r), dtype=np.float64) for r in raws]
     for d, pl in zip(sensors, planes):
         if pl.shape != (int(d["height"]), int(d["width"])):
@@ -242,6 +266,26 @@ def reconstruct(sensors, raws, params, pixels=None, want_fits=False, exhaustive=
     if fits is not None:
         out["fits"] = fits
     return out
+
+
+def sample_radiance_at(sensor: dict, x: int, row: int, y):
+    """(usable, f_hat, var_hat) of digital value(s) y at sensor pixel (x, row),
+    with the sensor's calibration frames.  y may be an array (then arrays)."""
+    lib = _load()
+    s = _sensor_struct(sensor)
+    i = int(row) * int(sensor["width"]) + int(x)
+    ys = np.atleast_1d(np.asarray(y, dtype=np.float64))
+    ok = np.empty(ys.shape, bool)
+    fh = np.empty(ys.shape)
+    vh = np.empty(ys.shape)
+    f = ctypes.c_double()
+    v = ctypes.c_double()
+    for k, yk in enumerate(ys):
+        ok[k] = bool(lib.orc_sample_radiance_at(ctypes.byref(s), i, float(yk), ctypes.byref(f), ctypes.byref(v)))
+        fh[k], vh[k] = f.value, v.value
+    if np.ndim(y) == 0:
+        return bool(ok[0]), float(fh[0]), float(vh[0])
+    return ok, fh, vh
 
 
 def sample_radiance(sensor: dict, y: float):
@@ -295,7 +339,8 @@ def gradients(sensors, raws, params, adapt=None, pixels=None, exhaustive=False):
     valid (n,)); invalid fits give a zero gradient."""
     lib = _load()
     ns = len(sensors)
-    sens = (_Sensor * ns)(*[_sensor_struct(d) for d in sensors])
+    structs = [_sensor_struct(d) for d in sensors]  # hold the calibration frames during the call
+    sens = (_Sensor * ns)(*structs)
     planes = [np.ascontiguousarray(np.asarray(r), dtype=np.float64) for r in raws]
     ptrs = (ctypes.c_void_p * ns)(*[pl.ctypes.data for pl in planes])
     prm = _params_struct(params, exhaustive)
@@ -336,7 +381,8 @@ def reconstruct_steered(sensors, raws, params, C, pixels=None, want_fits=False, 
     listed pixel).  Returns the same dict as reconstruct()."""
     lib = _load()
     ns = len(sensors)
-    sens = (_Sensor * ns)(*[_sensor_struct(d) for d in sensors])
+    structs = [_sensor_struct(d) for d in sensors]  # hold the calibration frames during the call
+    sens = (_Sensor * ns)(*structs)
     planes = [np.ascontiguousarray(np.asarray(r), dtype=np.float64) for r in raws]
     ptrs = (ctypes.c_void_p * ns)(*[pl.ctypes.data for pl in planes])
     prm = _params_struct(params, exhaustive)

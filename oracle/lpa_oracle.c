@@ -36,19 +36,31 @@ int orc_cfa_channel(int32_t cfa, int32_t x, int32_t y) {
   return table[cfa][2 * (y & 1) + (x & 1)];
 }
 
-/* Radiance estimate, Sec. 6 eq. (Efsi): f = (y - b) / (g t a n), with
- * exposure = n t and a = 1 (R6).  Variance estimate, Sec. 6.1
- * eq. (varianceestiamte): (g^2 t a n f + Var[r]) / (g^2 t^2 a^2 n^2), the
- * shot term evaluated at the noisy estimate f and clamped at zero (R6).
- * Saturated samples are excluded (end of Sec. 6.1, R5). */
-int orc_sample_radiance(const orc_sensor* s, double y, double* f_hat, double* var_hat) {
-  if (y >= s->saturation) return 0;
+/* Radiance estimate, Sec. 6 eq. (Efsi): f = (y - b_i) / (g t a_i n), with
+ * exposure = n t.  Variance estimate, Sec. 6.1 eq. (varianceestiamte):
+ * (g^2 t a_i n f + Var[r_i]) / (g^2 t^2 a_i^2 n^2), the shot term evaluated
+ * at the noisy estimate f and clamped at zero (R6).  Samples at or above the
+ * saturation frame are excluded (end of Sec. 6.1, R5), and so are defective
+ * pixels.  Without calibration frames b_i, a_i, Var[r_i] and the saturation
+ * level are the sensor's scalars, a_i = 1 (R23). */
+int orc_sample_radiance_at(const orc_sensor* s, int64_t i, double y, double* f_hat, double* var_hat) {
+  const int pix = i >= 0;
+  if (pix && s->defect && s->defect[i]) return 0;
+  const double sat = pix && s->sat ? s->sat[i] : s->saturation;
+  if (y >= sat) return 0;
+  const double b = pix && s->bias ? s->bias[i] : s->black_level;
+  const double a = pix && s->prnu ? s->prnu[i] : 1.0;
+  const double rv = pix && s->read_var ? s->read_var[i] : s->read_sigma * s->read_sigma;
   const double g = s->gain, e = s->exposure;
-  const double f = (y - s->black_level) / (g * e);
+  const double f = (y - b) / (g * e * a);
   const double shot = f > 0.0 ? f : 0.0;
   *f_hat = f;
-  *var_hat = (g * g * e * shot + s->read_sigma * s->read_sigma) / (g * g * e * e);
+  *var_hat = (g * g * e * a * shot + rv) / (g * g * e * e * a * a);
   return 1;
+}
+
+int orc_sample_radiance(const orc_sensor* s, double y, double* f_hat, double* var_hat) {
+  return orc_sample_radiance_at(s, -1, y, f_hat, var_hat);
 }
 
 /* ICI rule (not in the paper; R8).  Intervals [y_m - G sd_m, y_m + G sd_m] of
@@ -148,7 +160,8 @@ static int gather_support(const orc_sensor* sensors, int n_sensors, const double
       for (int x = x0; x <= x1; ++x) {
         if (orc_cfa_channel(S->cfa, x, y) != c) continue;
         double f, var;
-        if (!orc_sample_radiance(S, raw[s][(int64_t)y * S->width + x], &f, &var)) continue;
+        const int64_t pi = (int64_t)y * S->width + x;
+        if (!orc_sample_radiance_at(S, pi, raw[s][pi], &f, &var)) continue;
         double Xk, Yk;
         affine_apply(a, (double)x, (double)y, &Xk, &Yk);
         const double dx = Xk - X, dy = Yk - Y;
@@ -330,6 +343,11 @@ static int check_args(const orc_sensor* sensors, int32_t n_sensors, const double
     if (S->width < 1 || S->height < 1 || !(S->gain > 0) || !(S->exposure > 0) ||
         !(S->read_sigma > 0) || det == 0.0 || S->cfa < 0 || S->cfa > 3 || !raw[s])
       return -6;
+    const int64_t np = (int64_t)S->width * S->height;
+    for (int64_t i = 0; i < np; ++i)
+      if ((S->prnu && !(S->prnu[i] > 0)) || (S->read_var && !(S->read_var[i] >= 0)) ||
+          (S->bias && !isfinite(S->bias[i])) || (S->sat && isnan(S->sat[i])))
+        return -7;
   }
   return 0;
 }

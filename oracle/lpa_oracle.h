@@ -34,14 +34,18 @@
  *       h*kappa_G^2 (Sec. 5.3.1 suggests kappa_G = 2^-1/4; default 1);
  *   R4  sensor pixel centres sit at integer (col, row);
  *   R5  a sample is masked iff y >= saturation;
- *   R6  exposure = n_s t_s, non-uniformity a = 1, scalar bias frame; the shot
- *       term of the variance is clamped at 0 when y < b;
+ *   R6  exposure = n_s t_s; without calibration frames the non-uniformity
+ *       is a = 1 and the bias frame a scalar; the shot term of the variance is
+ *       clamped at 0 when y < b;
  *   R7  "invertible": N >= n and rho >= tau_inv, where rho is the smallest
  *       Cholesky pivot of the Jacobi-equilibrated normal matrix;
  *   R8  ICI with inclusive ties, Gamma-sigma intervals, sigma^2 the exact
  *       variance of the linear estimator (sandwich e0' A^-1 B A^-1 e0);
  *   R9  if no scale is valid at order M, fall back to order M-1, ..., 0 on the
- *       same samples; if nothing is valid the output is NaN.
+ *       same samples; if nothing is valid the output is NaN;
+ *   R23 per-pixel calibration frames (bias b_i, non-uniformity a_i, readout
+ *       variance, saturation frame; Sec. 6) are optional per sensor and frame
+ *       kind; a defect mask (not in the paper) excludes pixels like saturation.
  */
 #ifndef LPA_ORACLE_H
 #define LPA_ORACLE_H
@@ -67,6 +71,18 @@ typedef struct {
   double read_sigma;     /* sqrt(Var[r_s]) [DN]                              */
   double black_level;    /* b_s [DN]                                         */
   double saturation;     /* masked iff y >= saturation [DN]                  */
+  /* Optional per-pixel calibration frames (Sec. 6), row-major width*height;
+   * NULL selects the scalar above (R23):
+   *   bias      bias frame b_{s,i} [DN]                  (for black_level)
+   *   prnu      photo-response non-uniformity a_{s,i} > 0 (for a = 1)
+   *   read_var  readout variance Var[r_{s,i}] [DN^2]     (for read_sigma^2)
+   *   sat       saturation frame [DN]: masked iff y >= sat_i (for saturation)
+   *   defect    nonzero: a defective pixel, never used                     */
+  const double* bias;
+  const double* prnu;
+  const double* read_var;
+  const double* sat;
+  const uint8_t* defect;
 } orc_sensor;
 
 typedef struct {
@@ -122,6 +138,9 @@ int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* 
 /* Radiance estimate and variance estimate of one sample (Sec. 6, 6.1).
  * Returns 1 if the sample is usable (not saturated), 0 if masked. */
 int orc_sample_radiance(const orc_sensor* sensor, double y, double* f_hat, double* var_hat);
+/* The same for sensor pixel i = row * width + col, with its calibration
+ * frames where the sensor has them. */
+int orc_sample_radiance_at(const orc_sensor* sensor, int64_t i, double y, double* f_hat, double* var_hat);
 
 /* Channel (0 = R, 1 = G, 2 = B) of sensor pixel (x, y) for a CFA pattern. */
 int orc_cfa_channel(int32_t cfa, int32_t x, int32_t y);

@@ -25,13 +25,12 @@ MUTATIONS = [
     ("basis dx*dy -> dx*dx", "phi[4] = dx * dy;", "phi[4] = dx * dx;"),
     ("offset sign", "const double dx = Xk - X, dy = Yk - Y;", "const double dx = X - Xk, dy = Yk - Y;"),
     ("affine transposed", "*X = a[0] * x + a[1] * y + a[2];", "*X = a[0] * x + a[3] * y + a[2];"),
-    ("radiance without exposure", "const double f = (y - s->black_level) / (g * e);",
-     "const double f = (y - s->black_level) / g;"),
-    ("variance gain not squared", "*var_hat = (g * g * e * shot + s->read_sigma * s->read_sigma) / (g * g * e * e);",
-     "*var_hat = (g * e * shot + s->read_sigma * s->read_sigma) / (g * g * e * e);"),
-    ("variance without readout", "*var_hat = (g * g * e * shot + s->read_sigma * s->read_sigma) / (g * g * e * e);",
-     "*var_hat = (g * g * e * shot + 1e-30) / (g * g * e * e);"),
-    ("saturation exclusive", "if (y >= s->saturation) return 0;", "if (y > s->saturation) return 0;"),
+    ("radiance without exposure", "const double f = (y - b) / (g * e * a);", "const double f = (y - b) / (g * a);"),
+    ("variance gain not squared", "*var_hat = (g * g * e * a * shot + rv) / (g * g * e * e * a * a);",
+     "*var_hat = (g * e * a * shot + rv) / (g * g * e * e * a * a);"),
+    ("variance without readout", "*var_hat = (g * g * e * a * shot + rv) / (g * g * e * e * a * a);",
+     "*var_hat = (g * g * e * a * shot + 1e-30) / (g * g * e * e * a * a);"),
+    ("saturation exclusive", "if (y >= sat) return 0;", "if (y > sat) return 0;"),
     ("ICI strict tie", "if (lo_run <= hi_run)", "if (lo_run < hi_run)"),
     ("no equilibration", "At[i][j] = scale[i] * A[i][j] * scale[j];", "At[i][j] = A[i][j];"),
     ("back substitution index", "for (int k = i + 1; k < n; ++k) t -= L[k][i] * x[k];",
@@ -62,6 +61,18 @@ MUTATIONS = [
      "gather_support(sensors, n_sensors, raw, X, Y, 1, r, h, NULL, P->exhaustive, &list)",
      "gather_support(sensors, n_sensors, raw, X, Y, 0, r, h, NULL, P->exhaustive, &list)"),
     ("ellipse box not widened", "reff = r / sqrt(lmin);", "reff = r;"),
+    # per-pixel calibration frames (Sec. 6)
+    ("non-uniformity not in the radiance", "const double f = (y - b) / (g * e * a);",
+     "const double f = (y - b) / (g * e);"),
+    ("non-uniformity power in the variance", "(g * g * e * e * a * a)", "(g * g * e * e * a)"),
+    ("bias frame ignored", "const double b = pix && s->bias ? s->bias[i] : s->black_level;",
+     "const double b = s->black_level;"),
+    ("readout variance frame ignored",
+     "const double rv = pix && s->read_var ? s->read_var[i] : s->read_sigma * s->read_sigma;",
+     "const double rv = s->read_sigma * s->read_sigma;"),
+    ("saturation frame ignored", "const double sat = pix && s->sat ? s->sat[i] : s->saturation;",
+     "const double sat = s->saturation;"),
+    ("defect mask ignored", "if (pix && s->defect && s->defect[i]) return 0;", "if (0) return 0;"),
 ]
 
 
@@ -83,6 +94,7 @@ def test_pins_catch_planted_mistake(name, orig, bad):
         env = dict(os.environ, LPA_ORACLE_LIB_OVERRIDE=lib)
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                            os.path.join(ROOT, "tests", "test_oracle_calpa.py")],
+                            os.path.join(ROOT, "tests", "test_oracle_calpa.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_calib.py")],
                            cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake '{name}' passed every pin:\n{r.stdout[-2000:]}"
