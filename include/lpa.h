@@ -95,6 +95,27 @@ enum { LPA_STORE_FUSED = 0, LPA_STORE_FP32 = 1, LPA_STORE_FP16 = 2 };
  * LPA_ERR_OOM if the table exceeds the budget. */
 #define LPA_FLAG_PRECOMPUTED_WEIGHTS 0x2u
 
+/* Optional per-pixel calibration frames of one sensor (Sec. 6: the bias frame
+ * b_i, the photo-response non-uniformity a_i, the readout variance Var[r_i]
+ * and the saturation frame; plus a defect mask).  Host memory, width * height
+ * values each, row-major with no padding; copied to the device by
+ * lpa_create_rig (the caller may free them afterwards).  A NULL frame selects
+ * the sensor's scalar (black_level, a = 1, read_sigma^2, saturation; no
+ * defects).  With frames, a sample at pixel i is
+ *   f = (y - b_i) / (g n a_i),  Var f = (g max(y - b_i, 0) + Var[r_i]) / (g n a_i)^2,
+ * and it is masked iff y >= saturation_i or defect_i != 0.  Validation (at
+ * lpa_create_rig, LPA_ERR_INVALID_ARG): every b_i finite, a_i > 0 and finite,
+ * Var[r_i] > 0 and finite with the FP32 inverse variance of a dark sample in
+ * range, saturation_i not NaN.  Device memory: 16 bytes per pixel of a sensor
+ * that has any frame, charged to the context's budget until lpa_destroy_rig. */
+typedef struct {
+  const float* bias;       /* b_i [DN]                  */
+  const float* prnu;       /* a_i (> 0)                 */
+  const float* read_var;   /* Var[r_i] [DN^2] (> 0)     */
+  const float* saturation; /* masked iff y >= this [DN] */
+  const uint8_t* defect;   /* nonzero: never used       */
+} lpa_calib;
+
 /* One sensor of a rig (Sec. 3, Sec. 4, Sec. 6). */
 typedef struct {
   int32_t width, height; /* pixels                                          */
@@ -106,6 +127,7 @@ typedef struct {
   double read_sigma;     /* sqrt(Var[r_s]) [DN] (> 0)                       */
   double black_level;    /* b_s [DN]                                        */
   double saturation;     /* a sample is masked iff y >= saturation [DN]     */
+  const lpa_calib* calib;/* optional per-pixel frames (NULL: scalars only)  */
 } lpa_sensor_desc;
 
 typedef struct {

@@ -70,8 +70,47 @@ lpa_status validate_rig(const lpa_rig_desc* d) {
     }
     if (!std::isfinite(S.black_level) || !(S.saturation > S.black_level))
       return set_error(LPA_ERR_INVALID_ARG, "sensor %d: saturation must exceed black_level", s);
+    if (S.calib) {
+      const lpa_calib& C = *S.calib;
+      const int64_t n = (int64_t)S.width * S.height;
+      const double ge = S.gain * S.exposure;
+      for (int64_t i = 0; i < n; ++i) {
+        if (C.bias && !std::isfinite(C.bias[i]))
+          return set_error(LPA_ERR_INVALID_ARG, "sensor %d: bias frame not finite at pixel %lld", s, (long long)i);
+        const double a = C.prnu ? C.prnu[i] : 1.0;
+        if (!(a > 0) || !std::isfinite(a))
+          return set_error(LPA_ERR_INVALID_ARG, "sensor %d: non-uniformity must be > 0 (pixel %lld)", s, (long long)i);
+        const double rv = C.read_var ? C.read_var[i] : S.read_sigma * S.read_sigma;
+        const double v = rv / (ge * a * ge * a);
+        if (!(rv > 0) || !std::isfinite(rv) || !(v > 1e-30) || !(v < 1e30))
+          return set_error(LPA_ERR_INVALID_ARG, "sensor %d: readout variance invalid or out of FP32 range (pixel %lld)",
+                           s, (long long)i);
+        if (C.saturation && std::isnan(C.saturation[i]))
+          return set_error(LPA_ERR_INVALID_ARG, "sensor %d: saturation frame is NaN at pixel %lld", s, (long long)i);
+      }
+    }
   }
   return LPA_OK;
+}
+
+// Device plane of a sensor's calibration frames: per pixel (b_i, 1 / (g n a_i),
+// Var[r_i], saturation_i), the saturation -inf where the defect mask is set.
+static std::vector<float4> pack_calib(const lpa_sensor_desc& S) {
+  const lpa_calib& C = *S.calib;
+  const int64_t n = (int64_t)S.width * S.height;
+  std::vector<float4> out((size_t)n);
+  const double ge = S.gain * S.exposure;
+  for (int64_t i = 0; i < n; ++i) {
+    const double a = C.prnu ? C.prnu[i] : 1.0;
+    float4 c;
+    c.x = C.bias ? C.bias[i] : (float)S.black_level;
+    c.y = (float)(1.0 / (ge * a));
+    c.z = C.read_var ? C.read_var[i] : (float)(S.read_sigma * S.read_sigma);
+    c.w = C.saturation ? C.saturation[i] : (float)S.saturation;
+    if (C.defect && C.defect[i]) c.w = -INFINITY;
+    out[(size_t)i] = c;
+  }
+  return out;
 }
 
 lpa_status resolve_params(const lpa_params* p, Resolved* r) {
@@ -577,6 +616,10 @@ lpa_status lpa_create_ctx(int device, size_t hbm_budget_bytes, lpa_ctx** out) {
 static void rig_free(lpa_rig* rig) {
   (void)hipSetDevice(rig->ctx->device);
   if (rig->d_k) (void)hipFree(rig->d_k);
+  for (int s = 0; s < rig->n; ++s) {
+    if (rig->k[s].calib) (void)hipFree(const_cast<float4*>(rig->k[s].calib));
+    rig->ctx->used.fetch_sub(rig->calib_bytes[s]);
+  }
   stencil_free(rig);
   delete rig;
 }
@@ -609,15 +652,33 @@ lpa_status lpa_create_rig(lpa_ctx* ctx, const lpa_rig_desc* desc, lpa_rig** out)
   rig->n = desc->n_sensors;
   for (int s = 0; s < rig->n; ++s) {
     rig->desc[s] = desc->sensors[s];
+    rig->desc[s].calib = nullptr;  // the frames are copied below; the caller's pointers are not kept
     rig_constants(rig->desc[s], &rig->k[s]);
   }
-  // Device-resident copy of the calibration / noise constants.
   hipError_t e = hipSetDevice(ctx->device);
+  // Per-pixel calibration planes, resident until the rig is destroyed.
+  for (int s = 0; s < rig->n && e == hipSuccess; ++s) {
+    if (!desc->sensors[s].calib) continue;
+    const std::vector<float4> plane = pack_calib(desc->sensors[s]);
+    const size_t bytes = plane.size() * sizeof(float4);
+    if (ctx->used.fetch_add(bytes) + bytes > ctx->budget) {
+      ctx->used.fetch_sub(bytes);
+      rig_free(rig);
+      return set_error(LPA_ERR_OOM, "HBM budget of %zu bytes exceeded by calibration frames", ctx->budget);
+    }
+    rig->calib_bytes[s] = bytes;
+    void* d = nullptr;
+    e = hipMalloc(&d, bytes);
+    if (e == hipSuccess) {
+      rig->k[s].calib = static_cast<const float4*>(d);
+      e = hipMemcpy(d, plane.data(), bytes, hipMemcpyHostToDevice);
+    }
+  }
+  // Device-resident copy of the calibration / noise constants.
   if (e == hipSuccess) e = hipMalloc(&rig->d_k, sizeof(SensorK) * rig->n);
   if (e == hipSuccess) e = hipMemcpy(rig->d_k, rig->k, sizeof(SensorK) * rig->n, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    if (rig->d_k) (void)hipFree(rig->d_k);
-    delete rig;
+    rig_free(rig);
     return device_error(ctx, e, "rig tables");
   }
   {

@@ -145,6 +145,7 @@ struct lpa_rig {
   lpa_sensor_desc desc[LPA_MAX_SENSORS];
   lpa::SensorK k[LPA_MAX_SENSORS];  // host copy of the resident constants
   lpa::SensorK* d_k = nullptr;       // device-resident constants
+  size_t calib_bytes[LPA_MAX_SENSORS] = {0};  // budget charged for calibration planes
   // Pre-computed-weight tables, one per parameter class, built on first use
   // and kept until the rig is destroyed (a table may be read by queued work).
   struct Stencil {

@@ -40,6 +40,9 @@ struct SensorK {
   int8_t sub_oy[3][2];  // sub-lattice row parity
   int8_t nbox[2][kMaxScales][2]; // box size (sub-lattice points) [class][scale][x|y]
   int8_t pad_[5];
+  // per-pixel calibration (row-major width*height), or null for the scalars:
+  // (b_i, 1 / (g n a_i), Var[r_i], saturation_i), saturation -inf for defects
+  const float4* calib;
 };
 
 // Per-scale constants, per channel class (0: R and B, 1: G).

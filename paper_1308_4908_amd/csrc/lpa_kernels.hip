@@ -383,6 +383,16 @@ __device__ __forceinline__ float2 decode_dn(const SensorK& S, float y) {
   return make_float2(yb * S.inv_ge, __builtin_amdgcn_rcpf(var));
 }
 
+// The same with the pixel's calibration frames c = (b_i, 1 / (g n a_i),
+// Var[r_i], saturation_i) (Sec. 6 eq. Efsi and varianceestiamte with a_i and
+// the bias and saturation frames).
+__device__ __forceinline__ float2 decode_dn_cal(const SensorK& S, float y, float4 c) {
+  if (!(y < c.w)) return make_float2(0.f, 0.f);
+  const float yb = y - c.x;
+  const float var = __builtin_fmaf(S.gain, fmaxf(yb, 0.f), c.z) * (c.y * c.y);
+  return make_float2(yb * c.y, __builtin_amdgcn_rcpf(var));
+}
+
 __device__ __forceinline__ float2 decode_f16(const SensorK& S, __half h) {
   const float v = __half2float(h);
   if (__builtin_isinf(v)) return make_float2(0.f, 0.f);
@@ -395,14 +405,25 @@ template <int SRC>
 __device__ __forceinline__ float2 load_sample(const SensorK& S, int x, int y) {
   if (x < 0 || y < 0 || x >= S.width || y >= S.height) return make_float2(0.f, 0.f);
   const char* row = static_cast<const char*>(S.src) + (int64_t)y * S.pitch;
-  if constexpr (SRC == SRC_RAW_U16) {
-    return decode_dn(S, (float)reinterpret_cast<const uint16_t*>(row)[x]);
-  } else if constexpr (SRC == SRC_RAW_F32) {
-    return decode_dn(S, reinterpret_cast<const float*>(row)[x]);
+  if constexpr (SRC == SRC_RAW_U16 || SRC == SRC_RAW_F32) {
+    const float dn = SRC == SRC_RAW_U16 ? (float)reinterpret_cast<const uint16_t*>(row)[x]
+                                       : reinterpret_cast<const float*>(row)[x];
+    if (S.calib) return decode_dn_cal(S, dn, S.calib[(int64_t)y * S.width + x]);
+    return decode_dn(S, dn);
   } else if constexpr (SRC == SRC_PLANE_F32) {
     return reinterpret_cast<const float2*>(row)[x];
   } else {
-    return decode_f16(S, reinterpret_cast<const __half*>(row)[x]);
+    const __half h = reinterpret_cast<const __half*>(row)[x];
+    if (S.calib) {
+      // FP16 planes hold (y - b_i) 2^-bits; the frames give the pixel's scale and readout variance
+      const float v = __half2float(h);
+      if (__builtin_isinf(v)) return make_float2(0.f, 0.f);
+      const float4 c = S.calib[(int64_t)y * S.width + x];
+      const float yb = v * S.norm_decode;
+      const float var = __builtin_fmaf(S.gain, fmaxf(yb, 0.f), c.z) * (c.y * c.y);
+      return make_float2(yb * c.y, __builtin_amdgcn_rcpf(var));
+    }
+    return decode_f16(S, h);
   }
 }
 
@@ -1167,12 +1188,14 @@ __global__ void __launch_bounds__(256) prepass_kernel(const SensorK S, const voi
   const float dn = RAW_F32 ? reinterpret_cast<const float*>(rrow)[x]
                            : (float)reinterpret_cast<const uint16_t*>(rrow)[x];
   char* prow = static_cast<char*>(plane) + (int64_t)y * plane_pitch;
+  const bool cal = S.calib != nullptr;
+  const float4 c = cal ? S.calib[(int64_t)y * S.width + x] : make_float4(S.black, S.inv_ge, S.read_var, S.sat);
   if constexpr (TO_F16) {
-    const __half h = (dn < S.sat) ? __float2half_rn((dn - S.black) * norm_encode)
-                                  : __ushort_as_half((unsigned short)0x7C00u);
+    const __half h = (dn < c.w) ? __float2half_rn((dn - c.x) * norm_encode)
+                                : __ushort_as_half((unsigned short)0x7C00u);
     reinterpret_cast<__half*>(prow)[x] = h;
   } else {
-    reinterpret_cast<float2*>(prow)[x] = decode_dn(S, dn);
+    reinterpret_cast<float2*>(prow)[x] = cal ? decode_dn_cal(S, dn, c) : decode_dn(S, dn);
   }
 }
 

@@ -37,12 +37,17 @@ class LpaError(RuntimeError):
         self.status = status
 
 
+class Calib(ctypes.Structure):
+    _fields_ = [("bias", ctypes.c_void_p), ("prnu", ctypes.c_void_p), ("read_var", ctypes.c_void_p),
+                ("saturation", ctypes.c_void_p), ("defect", ctypes.c_void_p)]
+
+
 class SensorDesc(ctypes.Structure):
     _fields_ = [
         ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("cfa", ctypes.c_int32),
         ("bit_depth", ctypes.c_int32), ("affine", ctypes.c_double * 6), ("exposure", ctypes.c_double),
         ("gain", ctypes.c_double), ("read_sigma", ctypes.c_double), ("black_level", ctypes.c_double),
-        ("saturation", ctypes.c_double),
+        ("saturation", ctypes.c_double), ("calib", ctypes.POINTER(Calib)),
     ]
 
 
@@ -189,6 +194,27 @@ def sensor_desc(d: dict) -> SensorDesc:
     s.exposure, s.gain = float(d["exposure"]), float(d["gain"])
     s.read_sigma, s.black_level = float(d["read_sigma"]), float(d["black_level"])
     s.saturation = float(d["saturation"])
+    cal = d.get("calib")
+    if cal:
+        # per-pixel frames as float32 (uint8 defects), kept alive with the struct
+        # until lpa_create_rig has copied them
+        import numpy as np
+
+        c = Calib()
+        keep = []
+        shape = (s.height, s.width)
+        for name, key in (("bias", "bias"), ("prnu", "prnu"), ("read_var", "read_var"), ("saturation", "sat")):
+            if cal.get(key) is not None:
+                a = np.ascontiguousarray(np.asarray(cal[key], dtype=np.float32).reshape(shape))
+                keep.append(a)
+                setattr(c, name, a.ctypes.data)
+        if cal.get("defect") is not None:
+            a = np.ascontiguousarray(np.asarray(cal["defect"], dtype=np.uint8).reshape(shape))
+            keep.append(a)
+            c.defect = a.ctypes.data
+        keep.append(c)
+        s.calib = ctypes.pointer(c)
+        s._keep = keep
     return s
 
 
@@ -358,7 +384,8 @@ class Rig:
     """A camera rig: sensor calibration and noise constants resident on the device."""
 
     def __init__(self, ctx: Context, sensors: Sequence[dict]):
-        arr = (SensorDesc * len(sensors))(*[sensor_desc(d) for d in sensors])
+        descs = [sensor_desc(d) for d in sensors]  # holds any calibration frames until the rig has copied them
+        arr = (SensorDesc * len(sensors))(*descs)
         desc = RigDesc(len(sensors), arr)
         h = ctypes.c_void_p()
         check(lpa_create_rig(ctx.handle, ctypes.byref(desc), ctypes.byref(h)))

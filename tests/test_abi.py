@@ -38,9 +38,9 @@ def test_struct_layouts_match_header():
 
     from paper_1308_4908_amd import lpa
 
-    src = '#include "lpa.h"\n#include <stdio.h>\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n",' \
+    src = '#include "lpa.h"\n#include <stdio.h>\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n",' \
           'sizeof(lpa_sensor_desc),sizeof(lpa_rig_desc),sizeof(lpa_params),sizeof(lpa_frame),' \
-          'sizeof(lpa_output),sizeof(lpa_result),sizeof(lpa_tune_result));return 0;}\n'
+          'sizeof(lpa_output),sizeof(lpa_result),sizeof(lpa_tune_result),sizeof(lpa_calib));return 0;}\n'
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
@@ -48,7 +48,7 @@ def test_struct_layouts_match_header():
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         sizes = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     mine = [ctypes.sizeof(t) for t in (lpa.SensorDesc, lpa.RigDesc, lpa.Params, lpa.Frame, lpa.Output, lpa.Result,
-                                       lpa.TuneResult)]
+                                       lpa.TuneResult, lpa.Calib)]
     assert sizes == mine
 
 
