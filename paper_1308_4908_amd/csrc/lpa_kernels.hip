@@ -1136,9 +1136,11 @@ __global__ void __launch_bounds__(256) steer_kernel(const SteerArgs A) {
 // Persistent form: workgroups take tiles from a device counter until the
 // queue is exhausted; every workgroup reaches the exit test each round.  The
 // frame's order and single/multi-radius class select the fit code per tile
-// (a workgroup-uniform branch); all frames of one launch share SRC.
+// (a workgroup-uniform branch); all frames of one launch share SRC.  Compiled
+// for 4 waves per SIMD: order-2 tiles spill a few values around their solves,
+// as in fit_kernel_occ4, and the batch still runs faster than at 3 waves.
 template <int SRC>
-__global__ void __launch_bounds__(256) fit_batch_kernel(const BatchHeader* __restrict__ hdr,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) fit_batch_kernel(const BatchHeader* __restrict__ hdr,
                                                        const LaunchK* __restrict__ frames,
                                                        const int64_t* __restrict__ first_tile,
                                                        int* __restrict__ queue) {
