@@ -155,7 +155,7 @@ lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
       return device_error(ctx, e, "begin capture");
     (void)hipMemcpyAsync(d, h, L.copy_bytes, hipMemcpyHostToDevice, ctx->capture_stream);
     int32_t* q = reinterpret_cast<int32_t*>(d + L.queue_off);
-    (void)lpa_k_zero_i32(q, 1, ctx->capture_stream);
+    (void)lpa_k_zero_i32(q, 8, ctx->capture_stream);  // one tile counter per XCD range
     (void)lpa_k_fit_batch(reinterpret_cast<const BatchHeader*>(d), reinterpret_cast<const LaunchK*>(d + L.frames_off),
                           reinterpret_cast<const int64_t*>(d + L.first_off), q, src_kind, block, lds, grid,
                           ctx->capture_stream);

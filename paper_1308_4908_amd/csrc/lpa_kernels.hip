@@ -1133,12 +1133,17 @@ __global__ void __launch_bounds__(256) steer_kernel(const SteerArgs A) {
                        (float)(lb + (la - lb) * uy * uy), 0.f);
 }
 
-// Persistent form: workgroups take tiles from a device counter until the
-// queue is exhausted; every workgroup reaches the exit test each round.  The
-// frame's order and single/multi-radius class select the fit code per tile
-// (a workgroup-uniform branch); all frames of one launch share SRC.  Compiled
-// for 4 waves per SIMD: order-2 tiles spill a few values around their solves,
-// as in fit_kernel_occ4, and the batch still runs faster than at 3 waves.
+// Persistent form: the batch's tiles (frame-major, each frame's tiles
+// row-major) are split into kXcds contiguous ranges with a device counter
+// each.  A workgroup first takes tiles from the range of its own XCD
+// (workgroups are dispatched to the XCDs round-robin), so neighbouring tiles
+// share that XCD's L2, then from the other ranges in turn until all are
+// exhausted.  It moves to the next range only when a claim fails, at most
+// kXcds times, so every workgroup reaches the exit.  The frame's order and
+// single/multi-radius class select the fit code per tile (a
+// workgroup-uniform branch); all frames of one launch share SRC.  Compiled for
+// 4 waves per SIMD: order-2 tiles spill a few values around their solves, as
+// in fit_kernel_occ4, and the batch still runs faster than at 3 waves.
 template <int SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) fit_batch_kernel(const BatchHeader* __restrict__ hdr,
                                                        const LaunchK* __restrict__ frames,
@@ -1149,12 +1154,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
   __shared__ int next_tile;
   const int n_frames = hdr->n_frames;
   const int64_t total_tiles = hdr->total_tiles;
+  int range = blockIdx.x % kXcds, failed = 0;  // used by thread 0 only
   for (;;) {
-    if (threadIdx.x == 0) next_tile = atomicAdd(queue, 1);
+    if (threadIdx.x == 0) {
+      int t = -1;
+      while (failed < kXcds) {
+        const int64_t lo = total_tiles * range / kXcds, hi = total_tiles * (range + 1) / kXcds;
+        const int64_t c = lo + atomicAdd(&queue[range], 1);
+        if (c < hi) {
+          t = (int)c;
+          break;
+        }
+        range = (range + 1) % kXcds;
+        ++failed;
+      }
+      next_tile = t;
+    }
     __syncthreads();
     const int t = next_tile;
     __syncthreads();
-    if ((int64_t)t >= total_tiles) break;
+    if (t < 0) break;
     // frame owning global tile t (binary search over first-tile offsets)
     int lo = 0, hi = n_frames - 1;
     while (lo < hi) {
