@@ -197,3 +197,20 @@ def test_invalid_frames_rejected(torch_mod, ctx):
         with pytest.raises(LpaError) as e:
             Rig(ctx, [dict(base, calib=bad)])
         assert e.value.status == lpa.ERR_INVALID_ARG
+
+
+def test_calpa_with_frames(torch_mod, ctx):
+    """CALPA's three passes decode with the frames too: the end-to-end chain
+    against the oracle's chain on the same frames."""
+    base = R.random_rig(3, 64, 64, [1.0, 1 / 8, 1 / 64], 1.5, 0.2, 8700, **configs.NOISE)
+    sensors = calibrated(base, 8700)
+    raws = configs.capture_all(EdgeScene(64, 64, 8700, n_lines=8), base, 8700)
+    adapt = {"alpha": 0.2, "lambda1": 1.0, "lambda2": 0.001, "grad_radius": 2.0, "grad_order": 1,
+             "grad_halfwin": 2, "max_stretch": 2.0}
+    params = configs.lpa_params(64, 64, 2, [1.0, 2.0, 3.0], mode="calpa", adapt=adapt)
+    _say("[gpu] calibration frames, CALPA")
+    rgb, smap, sd = run(torch_mod, ctx, sensors, raws, params)
+    orc = oracle.reconstruct_adaptive(sensors, raws, params, adapt, want_fits=True)
+    st = compare(rgb, smap, orc, sensors, 2, extra_tol=1e-5, gpu_sd=sd)
+    _say(f"  stats {st}")
+    assert st["agree_frac"] > 0.999

@@ -252,3 +252,20 @@ def test_refused_where_not_applicable(torch_mod, ctx):
     rig2.close()
     torch_mod.cuda.synchronize()
     assert torch_mod.all(out == 7.0)
+
+
+@pytest.mark.parametrize("cfa", ["GRBG", "BGGR"])
+def test_other_cfa_layouts_and_odd_sizes(torch_mod, ctx, cfa):
+    """The tables take each sensor's sub-lattice parities from its CFA; odd
+    sensor and output sizes leave ragged tiles on both axes."""
+    sensors = [dict(s, cfa=cfa) for s in translation_rig(3, 77, 7700)]
+    sensors = [dict(s, height=59) for s in sensors]
+    scene = EdgeScene(77, 59, 7700, n_lines=8)
+    raws = configs.capture_all(scene, sensors, 7700)
+    params = configs.lpa_params(75, 57, 2, [1.0, 2.0, 3.0], out_affine=[1, 0, 1.0, 0, 1, 1.0])
+    _say(f"[gpu] stencil cfa={cfa} odd sizes")
+    rgb, smap, sd = run(torch_mod, ctx, sensors, raws, params)
+    orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
+    st = compare(rgb, smap, orc, sensors, 2, gpu_sd=sd)
+    _say(f"  stats {st}")
+    assert st["agree_frac"] > 0.999
