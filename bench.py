@@ -249,8 +249,8 @@ def main():
         print(json.dumps({"copy_probe_bytes": n, "launches": 3}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md but not run).", file=sys.stderr)
+        print("bench.py measures one GPU (--gpus 1): frames and output row bands shard across GPUs without "
+              "collectives, but that form is not run here.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -60,7 +60,7 @@ enum {
   LPA_ERR_INVALID_ARG = -1, /* argument failed validation; nothing enqueued    */
   LPA_ERR_OOM = -2,         /* device memory or HBM budget exhausted            */
   LPA_ERR_DEVICE = -3,      /* HIP runtime / device error (context now failed) */
-  LPA_ERR_UNSUPPORTED = -4, /* valid request this build cannot run              */
+  LPA_ERR_UNSUPPORTED = -4, /* valid request the library does not run           */
   LPA_ERR_INTERNAL = -5
 };
 
