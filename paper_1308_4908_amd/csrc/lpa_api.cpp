@@ -1,6 +1,9 @@
-// lpa_api.cpp -- the C ABI of include/lpa.h: contexts, rigs, argument
-// validation, launch-descriptor construction and the single-frame paths.
-// Batched and served paths live in lpa_batch.cpp / lpa_serve.cpp.
+// lpa_api.cpp -- the C ABI of include/lpa.h: contexts, rigs (with their
+// resident calibration planes), argument validation, launch-descriptor
+// construction and the single-frame paths (isotropic LPA, CALPA's three
+// passes, pre-computed weights).  Batched and served paths live in
+// lpa_batch.cpp / lpa_serve.cpp, the pre-computed-weight tables in
+// lpa_stencil.cpp, the tuner in lpa_tune.cpp.
 #include "lpa_host.hpp"
 
 #include <algorithm>

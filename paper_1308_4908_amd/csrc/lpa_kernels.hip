@@ -15,6 +15,19 @@
 // The normal matrix of a polynomial basis has Hankel structure: entry (i, j)
 // is the weighted moment of the monomial phi_i phi_j, so an order-2 fit needs
 // 15 distinct moments (not 21) and its variance matrix 15 more.
+//
+// Kernel families, all built on the same staging, solve and ICI code:
+//   fit_kernel / fit_kernel_occ4   the isotropic fit (3- and 4-wave budgets);
+//   fit_batch_kernel               its persistent form over many frames;
+//   grad_kernel, steer_kernel,     adaptive anisotropic windows (Sec. 5.4,
+//   fit_kernel_steer               5.5): G gradients, steering matrices, the
+//                                  fit with the window d^T C d;
+//   fit_kernel_stencil(_occ4)      pre-computed window weights for
+//                                  translation-only rigs (scalar-load tables);
+//   prepass_kernel                 raw -> FP32 or FP16 planes.
+// Sensors with per-pixel calibration frames (bias, non-uniformity, readout
+// variance, saturation, defects; Sec. 6) are decoded with them wherever a raw
+// sample is read.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
