@@ -7,9 +7,10 @@ there, in FP64, single-threaded.  It shares no code with the GPU library.
 
 Rig and parameter descriptions are plain dicts (see ``synth.rig``):
 sensor keys  width, height, cfa, affine(6), exposure, gain, read_sigma,
-             black_level, saturation
+             black_level, saturation; optional calib: per-pixel frames
+             (height x width) bias, prnu, read_var, sat, defect (Sec. 6)
 param keys   out_w, out_h, out_affine(6), order, radii, h (optional), gamma,
-             green_ratio, tau_inv
+             green_ratio, tau_inv; for CALPA the adapt dict (reconstruct_adaptive)
 """
 from __future__ import annotations
 
