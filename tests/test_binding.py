@@ -1,6 +1,7 @@
 """The Python binding marshals plain dicts and arrays into the C ABI structs
 faithfully (CPU only: nothing is launched)."""
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -8,6 +9,9 @@ import torch
 
 from paper_1308_4908_amd import lpa
 from synth import configs
+from synth import rig as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_params_struct_fields():
@@ -66,3 +70,43 @@ def test_output_struct_checks_layout():
         lpa.output_struct(torch.zeros((5, 7, 4)))
     with pytest.raises(ValueError):
         lpa.output_struct(torch.zeros((5, 3, 7)).permute(0, 2, 1))
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """There is no fallback path: loading a library that is not built raises."""
+    import subprocess
+    import sys
+
+    code = ("from paper_1308_4908_amd import lpa\n"
+            f"lpa.LIB_PATH = {str(tmp_path / 'liblpa.so')!r}\n"
+            "try:\n    lpa.load()\nexcept ImportError as e:\n    print('raised', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert "raised" in r.stdout and "not built" in r.stdout
+
+
+def test_sensor_calibration_frames_marshalled():
+    """Per-pixel frames are passed as float32 planes (uint8 defects) of the
+    sensor's shape; absent frames stay NULL."""
+    import ctypes
+
+    import numpy as np
+
+    s = dict(R.make_sensor(4, 3, [1, 0, 0, 0, 1, 0], 1.0),
+             calib={"bias": np.full((3, 4), 60.0), "defect": np.eye(3, 4, dtype=np.uint8)})
+    d = lpa.sensor_desc(s)
+    c = d.calib.contents
+    bias = np.ctypeslib.as_array(ctypes.cast(c.bias, ctypes.POINTER(ctypes.c_float)), shape=(12,))
+    assert np.all(bias == 60.0)
+    defect = np.ctypeslib.as_array(ctypes.cast(c.defect, ctypes.POINTER(ctypes.c_uint8)), shape=(12,))
+    assert defect.reshape(3, 4)[1, 1] == 1 and defect.sum() == 3
+    assert not c.prnu and not c.read_var and not c.saturation
+    assert not lpa.sensor_desc(R.make_sensor(4, 3, [1, 0, 0, 0, 1, 0], 1.0)).calib
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=ROOT, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
