@@ -237,6 +237,12 @@ void rig_constants(const lpa_sensor_desc& S, SensorK* k) {
   }
 }
 
+// LDS the fit kernels declare statically beside the staged tile (one Region
+// per sensor, 128 bytes, and the persistent kernel's tile index), rounded up:
+// the staged tile and these arrays together stay within the per-workgroup
+// limit.
+constexpr int64_t kStaticLdsReserve = 256;
+
 // Fill the launch-dependent parts of a descriptor.  Returns false if the
 // LDS footprint of the requested tile does not fit.
 lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output* out, int src_kind,
@@ -326,7 +332,7 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output*
     S.reg_h = (int)std::ceil(ey + 2 * wmy) + 8;
     S.lds_off = lds;
     lds += S.reg_w * S.reg_h;
-    if ((int64_t)lds * 8 > lpa_k_fit_max_lds_bytes())
+    if ((int64_t)lds * 8 + kStaticLdsReserve > lpa_k_fit_max_lds_bytes())
       return set_error(LPA_ERR_UNSUPPORTED, "tile %dx%d needs more than %d bytes of LDS", tile_w, tile_h,
                        lpa_k_fit_max_lds_bytes());
   }
@@ -555,9 +561,11 @@ lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_para
     th = tc.tile_h;
   }
   LaunchK K;
-  // the pre-computed-weight kernel needs one parity class per wave: 16 x 16
-  st = (plain || stencil) ? build_launch(rig, R, out, src_kind, srcs, pitches, 16, 16, &K)
-                          : build_launch_fit(rig, R, out, src_kind, srcs, pitches, tw, th, &K);
+  // The pre-computed-weight kernel needs one parity class per wave: 16 x 16.
+  // The other forms fall back to smaller tiles when wide windows over many
+  // sensors overflow the LDS of the preferred one (16 x 16 for the plain form).
+  st = stencil ? build_launch(rig, R, out, src_kind, srcs, pitches, 16, 16, &K)
+               : build_launch_fit(rig, R, out, src_kind, srcs, pitches, tw, th, &K);
   if (st != LPA_OK) return st;
   K.occupancy = tc.occupancy;
   if (stencil) {
