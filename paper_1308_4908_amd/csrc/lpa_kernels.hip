@@ -95,40 +95,71 @@ __device__ __forceinline__ bool acc_sample(Acc<ORDER, ICI>& a, float dx, float d
   const float x2 = dx * dx, y2 = dy * dy;
   const float r2 = window_r2<STEER>(dx, dy, x2, y2, sc);
   if (r2 < reach2) {
-    float mono[n_mom<ORDER>()];
-    mono[0] = 1.f;
-    if constexpr (ORDER >= 1) {
-      mono[1] = dx;
-      mono[2] = dy;
-      mono[3] = x2;
-      mono[4] = dx * dy;
-      mono[5] = y2;
-    }
-    if constexpr (ORDER >= 2) {
-      mono[6] = mono[3] * dx;
-      mono[7] = mono[3] * dy;
-      mono[8] = mono[4] * dy;
-      mono[9] = mono[5] * dy;
-      mono[10] = mono[3] * mono[3];
-      mono[11] = mono[6] * dy;
-      mono[12] = mono[3] * mono[5];
-      mono[13] = mono[8] * dy;
-      mono[14] = mono[5] * mono[5];
-    }
-    const float kw = fmaxf(__builtin_amdgcn_exp2f(-r2) - e_edge, 0.f);
+    // K = exp2(-r2) - e_edge never exceeds 1, so clamping to [0, 1] is the
+    // cut at zero (one instruction: the subtraction's clamp modifier).
+    const float kw = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-r2) - e_edge, 0.f, 1.f);
     const float w = kw * iv;
-    const float wf = w * f;
-    a.m[0] += w;
+    if constexpr (ORDER >= 2) {
+      // Order 2: the weighted products w d^a for |a| <= 2 are the moments of
+      // degree <= 2 and the basis terms of b; each moment of degree 3 and 4 is
+      // one of them times dx, dy, dx^2 or dy^2 (one FMA).  B's degree <= 2
+      // terms are K times the same products, its higher ones K w d^a times
+      // the same factors.  Indices follow midx (degree-major, x power
+      // descending): 6..9 = x^3, x^2 y, x y^2, y^3; 10..14 = x^4 .. y^4.
+      const float wx = w * dx, wy = w * dy;
+      const float wxx = wx * dx, wxy = wx * dy, wyy = wy * dy;
+      const float p[6] = {w, wx, wy, wxx, wxy, wyy};
 #pragma unroll
-    for (int k = 1; k < n_mom<ORDER>(); ++k) a.m[k] = __builtin_fmaf(w, mono[k], a.m[k]);
-    a.b[0] += wf;
+      for (int k = 0; k < 6; ++k) a.m[k] += p[k];
+      a.m[6] = __builtin_fmaf(wxx, dx, a.m[6]);
+      a.m[7] = __builtin_fmaf(wxx, dy, a.m[7]);
+      a.m[8] = __builtin_fmaf(wyy, dx, a.m[8]);
+      a.m[9] = __builtin_fmaf(wyy, dy, a.m[9]);
+      a.m[10] = __builtin_fmaf(wxx, x2, a.m[10]);
+      a.m[11] = __builtin_fmaf(wxy, x2, a.m[11]);
+      a.m[12] = __builtin_fmaf(wxx, y2, a.m[12]);
+      a.m[13] = __builtin_fmaf(wxy, y2, a.m[13]);
+      a.m[14] = __builtin_fmaf(wyy, y2, a.m[14]);
 #pragma unroll
-    for (int k = 1; k < n_basis<ORDER>(); ++k) a.b[k] = __builtin_fmaf(wf, mono[k], a.b[k]);
-    if constexpr (ICI) {
-      const float w2 = w * kw;
-      a.B[0] += w2;
+      for (int k = 0; k < 6; ++k) a.b[k] = __builtin_fmaf(f, p[k], a.b[k]);
+      if constexpr (ICI) {
 #pragma unroll
-      for (int k = 1; k < n_mom<ORDER>(); ++k) a.B[k] = __builtin_fmaf(w2, mono[k], a.B[k]);
+        for (int k = 0; k < 6; ++k) a.B[k] = __builtin_fmaf(kw, p[k], a.B[k]);
+        const float kxx = kw * wxx, kxy = kw * wxy, kyy = kw * wyy;
+        a.B[6] = __builtin_fmaf(kxx, dx, a.B[6]);
+        a.B[7] = __builtin_fmaf(kxx, dy, a.B[7]);
+        a.B[8] = __builtin_fmaf(kyy, dx, a.B[8]);
+        a.B[9] = __builtin_fmaf(kyy, dy, a.B[9]);
+        a.B[10] = __builtin_fmaf(kxx, x2, a.B[10]);
+        a.B[11] = __builtin_fmaf(kxy, x2, a.B[11]);
+        a.B[12] = __builtin_fmaf(kxx, y2, a.B[12]);
+        a.B[13] = __builtin_fmaf(kxy, y2, a.B[13]);
+        a.B[14] = __builtin_fmaf(kyy, y2, a.B[14]);
+      }
+    } else {
+      // orders 0 and 1: monomials, then one FMA per moment with w, w f, w K
+      float mono[n_mom<ORDER>()];
+      mono[0] = 1.f;
+      if constexpr (ORDER >= 1) {
+        mono[1] = dx;
+        mono[2] = dy;
+        mono[3] = x2;
+        mono[4] = dx * dy;
+        mono[5] = y2;
+      }
+      const float wf = w * f;
+      a.m[0] += w;
+#pragma unroll
+      for (int k = 1; k < n_mom<ORDER>(); ++k) a.m[k] = __builtin_fmaf(w, mono[k], a.m[k]);
+      a.b[0] += wf;
+#pragma unroll
+      for (int k = 1; k < n_basis<ORDER>(); ++k) a.b[k] = __builtin_fmaf(wf, mono[k], a.b[k]);
+      if constexpr (ICI) {
+        const float w2 = w * kw;
+        a.B[0] += w2;
+#pragma unroll
+        for (int k = 1; k < n_mom<ORDER>(); ++k) a.B[k] = __builtin_fmaf(w2, mono[k], a.B[k]);
+      }
     }
     return w > 0.f;
   }
