@@ -240,13 +240,18 @@ lpa_status lpa_destroy_rig(lpa_rig* rig);
 
 /* Reconstruct one frame, stream-ordered on `hip_stream` (a hipStream_t; NULL
  * = the null stream).  raw and out are device pointers borrowed until the
- * stream passes this work.  Returns after enqueueing. */
+ * stream passes this work.  Returns after enqueueing.  When wide windows over
+ * many sensors make a tile's staged samples overflow the workgroup's 64 KiB
+ * of LDS, the launch uses smaller tiles (down to 4x4 output pixels); a window
+ * no tile can stage, or one more than 240 sensor pixels across, returns
+ * LPA_ERR_UNSUPPORTED before anything is enqueued. */
 lpa_status lpa_reconstruct(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
                            const lpa_output* out, void* hip_stream);
 
 /* The plain per-frame form: FP32 radiance / inverse-variance planes from a
- * separate pre-pass launch, then one fit launch with a fixed 16x16 tile (no
- * tuning).  Same results contract as lpa_reconstruct. */
+ * separate pre-pass launch, then one fit launch with 16x16 tiles (no tuning;
+ * smaller tiles only where the LDS rule above requires them).  Same results
+ * contract as lpa_reconstruct. */
 lpa_status lpa_reconstruct_plain(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
                                  const lpa_output* out, void* hip_stream);
 
