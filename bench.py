@@ -38,7 +38,7 @@ HBM_TBPS = 8.0
 RADII = [1.0, 2.0, 3.0, 4.0]
 
 # Algorithmic FLOP per unit of work for an order-2 (n = 6) fit with ICI,
-# counting FMA = 2 and mul/add/exp/rcp = 1 ("Measurement"):
+# counting FMA = 2 and mul/add/exp/rcp = 1:
 FLOP_PER_SAMPLE = 19          # transform 8, |d|^2 3, quadratic basis 3, radiance 1, inverse variance 4
 FLOP_PER_SAMPLE_SCALE = 111   # window 3, weight 1, basis products 5, A 42, b 12, ICI B 48
 FLOP_PER_SOLVE = 294          # 6x6 equilibrated Cholesky + C0 + variance
@@ -47,6 +47,17 @@ FLOP_PER_SOLVE = 294          # 6x6 equilibrated Cholesky + C0 + variance
 # sample-radius update w f and K w (2) and the 36 moment FMAs (72).
 FLOP_PER_SAMPLE_STENCIL = 5
 FLOP_PER_SAMPLE_SCALE_STENCIL = 74
+
+# The paper's own timings (Sec. 8), for context only: order-0 LPA with one
+# fixed window, 4 sensors to a 2336 x 1752 output on a GeForce GTX 680, at
+# 26 fps with pre-computed window weights and 7 fps with per-pixel weights.
+PAPER_CONTEXT = {
+    "source": "Sec. 8, CUDA implementation", "hardware": "NVIDIA GeForce GTX 680",
+    "workload": "order-0 LPA, one fixed window, 4 sensors, 2336x1752 output",
+    "fps_precomputed_weights": 26, "mpix_s_precomputed_weights": round(26 * 2336 * 1752 / 1e6, 1),
+    "fps_per_pixel_weights": 7, "mpix_s_per_pixel_weights": round(7 * 2336 * 1752 / 1e6, 1),
+    "note": "not this workload (order 2 with ICI over four radii here); no timing of order 1 or 2 or of ICI is given",
+}
 
 
 def algorithmic_flops(raws, sensors, n_pixels: int) -> float:
@@ -408,6 +419,7 @@ def main():
         "speedup_vs_plain": round(value / plain["value"], 3) if plain else None,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
         "batched": batched,
         "served": served,
         "wall_s_timed": round(wall, 3),
