@@ -268,8 +268,10 @@ lpa_status lpa_reconstruct_batch(lpa_ctx* ctx, int32_t n, lpa_rig* const* rigs,
  * raw planes are copied into a device slot when the HBM budget admits the
  * frame; frames admitted while others run are batched into the next launch,
  * which overlaps the running one on a second stream.  raw and out are
- * borrowed until lpa_poll reports a terminal status.  Returns LPA_AGAIN if
- * the admission queue (1024 frames) is full. */
+ * borrowed until lpa_poll reports a terminal status.  The library's copies
+ * and launches run on its own non-blocking streams, unordered with the
+ * caller's: work the caller enqueued on raw or out must be complete before
+ * the call.  Returns LPA_AGAIN if the admission queue (1024 frames) is full. */
 lpa_status lpa_submit(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
                       const lpa_output* out, int64_t arrival_ns, uint64_t* ticket);
 /* Non-blocking: LPA_NOT_READY until the frame is done; then its result.  A

@@ -637,7 +637,9 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
       const double Yb = S.fwd[3] * xb + S.fwd[4] * yb + S.fwd[5];
       const float c0x = (float)((Xb - Xj) * cs);
       const float c0y = (float)((Yb - Yj) * cs);
-      const float2* p0 = plane + (yb - R.y0) * R.w + (xb - R.x0);
+      // row index times pitch: both are below 2^24 (the box lies inside the
+      // staged region), so the full-rate 24-bit multiply is exact
+      const float2* p0 = plane + __mul24(yb - R.y0, R.w) + (xb - R.x0);
       walk_box(p0, row_step, nx, ny, c0x, c0y, sax, say, sbx, sby, fn);
     }
   }

@@ -107,6 +107,8 @@ def _serve(torch, ctx, items, host_pinned=True):
         out = torch.full((p["out_h"], p["out_w"], 3), -1.0, device="cuda")
         smap = torch.zeros((p["out_h"], p["out_w"], 3), dtype=torch.uint8, device="cuda")
         outs.append((out, smap))
+        # the library's streams are not ordered after torch's: the fills must be done
+        torch.cuda.synchronize()
         t = None
         while t is None:
             t = rig.submit(hs, p, out, smap, arrival_ns=0, host=True)

@@ -161,6 +161,7 @@ def test_batch_and_serving_equal_alone(torch_mod, ctx):
     for o in outs:
         assert np.array_equal(o.cpu().numpy(), alone[0], equal_nan=True)
     out = torch.full((48, 80, 3), -1.0, device="cuda")
+    torch.cuda.synchronize()  # the library's streams are not ordered after torch's
     t = None
     while t is None:
         t = rig.submit([torch.from_numpy(r).pin_memory() for r in raws], params, out, host=True)
