@@ -216,9 +216,11 @@ def test_bilinear_demosaic_special_case():
 #   int_0^r K rho^3 drho = h^2/2 (1 - e (1 + r^2/h)) - r^4 e / 4,   e = exp(-r^2/h).
 # A dense aligned sensor (spacing 1/8) approximates the integral.
 # --------------------------------------------------------------------------
-def test_window_second_moment_closed_form():
+@pytest.mark.parametrize("h_given", [0.0, 0.4, 1.5])
+def test_window_second_moment_closed_form(h_given):
+    """h_given = 0 selects the default 2 r^2 / 9; the closed form holds for any h."""
     r = 2.0
-    h = 2 * r * r / 9
+    h = h_given if h_given > 0 else 2 * r * r / 9
     e = math.exp(-r * r / h)
     i1 = h / 2 * (1 - e) - r * r * e / 2
     i3 = h * h / 2 * (1 - e * (1 + r * r / h)) - r ** 4 * e / 4
@@ -230,7 +232,7 @@ def test_window_second_moment_closed_form():
     y, x = np.mgrid[0:n, 0:n] * step
     c0 = 5000.0
     raw = c0 + (x - X0) ** 2
-    params = _params(1, 1, 0, [r], out_affine=[0, 0, X0, 0, 0, Y0])
+    params = _params(1, 1, 0, [r], out_affine=[0, 0, X0, 0, 0, Y0], h=[h_given])
     res = oracle.reconstruct([s], [raw], params)
     got = res["rgb"][0] - c0
     # discretisation error at spacing 1/16 is well below 1%; the plausible
