@@ -110,3 +110,18 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=ROOT, capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_bench_traffic_only_for_the_profiled_source(monkeypatch):
+    """The benchmark reports the counter-measured HBM traffic only while the
+    kernel sources hash to the value the counters were taken on."""
+    import sys
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    key = "fit_kernel<2,ICI,RAW_U16>"
+    got = bench.measured_traffic(key)
+    assert got is not None and got > 0  # the committed counters match the committed sources
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
+    assert bench.measured_traffic(key) is None
