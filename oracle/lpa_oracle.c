@@ -485,7 +485,7 @@ int orc_steering(const orc_params* P, const orc_adapt* A, const double* grad_pla
                  const int32_t* pixels, int64_t n_pixels, double* C, double* diag) {
   if (!P || !A || !grad_plane || !C) return -1;
   if (!pixels && n_pixels != (int64_t)P->out_w * P->out_h) return -5;
-  if (A->grad_halfwin < 0 || !(A->max_stretch >= 1.0) || !(A->alpha >= 0.0) || !(A->lambda1 >= 0.0) ||
+  if (A->grad_halfwin < 0 || !(A->max_stretch >= 1.0) || !(A->alpha >= 0.0) || !(A->lambda1 > 0.0) ||
       !(A->lambda2 >= 0.0))
     return -8;
   const int q = A->grad_halfwin;
