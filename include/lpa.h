@@ -71,13 +71,22 @@ enum { LPA_MEM_DEVICE = 0, LPA_MEM_HOST = 1 }; /* where lpa_frame.raw points    
 /* Sample storage between raw decode and the fit:
  *   FUSED   raw samples are decoded straight into LDS by the fit kernel;
  *   FP32    a pre-pass writes FP32 radiance + FP32 inverse variance planes;
- *   FP16    a pre-pass writes FP16 normalised radiance (y - b) * 2^-bit_depth,
- *           round-to-nearest-even, +Inf for masked samples; the fit kernel
- *           decodes radiance and variance from it. */
+ *   FP16    a pre-pass writes the FP16 normalised value (y - o) * 2^-bit_depth,
+ *           round-to-nearest-even, +Inf for masked samples (masking is
+ *           decided on the raw value); the fit kernel decodes radiance and
+ *           variance from it.  For ADCs of up to 12 bits o = 2^(bit_depth-1):
+ *           FP16 holds every integer in [-2048, 2048] exactly, so the raw
+ *           values are stored without loss and the results equal FUSED's bit
+ *           for bit.  Deeper ADCs use o = black_level: values up to 2048 DN
+ *           above it are exact, larger ones carry 2^-12 relative rounding. */
 enum { LPA_STORE_FUSED = 0, LPA_STORE_FP32 = 1, LPA_STORE_FP16 = 2 };
 
 /* lpa_params.flags */
-#define LPA_FLAG_NO_FP64_FALLBACK 0x1u /* never refine ill-conditioned order-2 solves in FP64 */
+/* Valid fits keep the values of their FP32 moments: no FP64 values for fits
+ * whose pivot is below tau_fp64 nor for the value_tol target.  Fits whose
+ * validity the FP32 pivots cannot decide are still decided (and then valued)
+ * on FP64 moments. */
+#define LPA_FLAG_NO_FP64_FALLBACK 0x1u
 /* Pre-computed window weights (Sec. 8: the paper precomputes the weights for
  * registered sensors at the output resolution).  When every sensor map T_s
  * and the output map O are translations (linear parts exactly the identity),
@@ -173,10 +182,22 @@ typedef struct {
   int32_t grad_halfwin;   /* >= 0                                                   */
   int32_t pad_;
   double alpha;           /* structure sensitivity >= 0                             */
-  double lambda1, lambda2;/* >= 0                                                   */
+  double lambda1, lambda2;/* lambda1 > 0 (flat windows: s1 = s2 = 0), lambda2 >= 0   */
   double grad_radius;     /* reference-plane units (<= 0: default)                  */
   double grad_h;          /* <= 0: 2 grad_radius^2 / 9                              */
   double max_stretch;     /* >= 1 (0: 2)                                            */
+  /* Accuracy target of the output values, relative to max(|C0|, floor) with
+   * floor = 1 / max_s(g_s n_s) (one DN of the most exposed sensor).  Moments
+   * are accumulated in FP32; with every fit the kernel computes a bound S on
+   * how far the rounding of its moment terms can move C0 (per unit relative
+   * rounding; an upper estimate of the componentwise condition of C0 in the
+   * moment terms), and where 16 * 2^-24 * S exceeds value_tol times the scale
+   * above, the chosen fit of that output is recomputed from FP64 products
+   * and sums of the same samples.  In HDR windows C0 is often a small
+   * difference of large terms, so a few percent of the outputs of the
+   * benchmark frame take this path.  0 selects 1e-4; a negative value never
+   * recomputes. */
+  double value_tol;
 } lpa_params;
 
 enum { LPA_MODE_LPA = 0, LPA_MODE_CALPA = 1 };
@@ -209,6 +230,11 @@ typedef struct {
   int64_t grad_map_pitch;
   float* steer_map;
   int64_t steer_map_pitch;
+  /* Optional device pointer to two counters, written stream-ordered after the
+   * frame: [0] outputs (pixel x channel) whose value came from an FP64 solve,
+   * [1] outputs with no valid fit (NaN).  lpa_submit also reports them in
+   * lpa_result. */
+  uint64_t* stats;
 } lpa_output;
 
 /* Status and timestamps of a submitted frame (CLOCK_MONOTONIC ns). */
@@ -216,6 +242,8 @@ typedef struct {
   int32_t status;         /* LPA_OK, LPA_NOT_READY or an error */
   int32_t batch_size;     /* frames in the launch that ran it  */
   int64_t t_arrival_ns, t_admit_ns, t_start_ns, t_done_ns;
+  uint64_t n_fp64;        /* outputs valued by an FP64 solve (as lpa_output.stats[0]) */
+  uint64_t n_invalid;     /* outputs with no valid fit (NaN) */
 } lpa_result;
 
 typedef struct lpa_ctx lpa_ctx;
@@ -272,10 +300,15 @@ lpa_status lpa_reconstruct_batch(lpa_ctx* ctx, int32_t n, lpa_rig* const* rigs,
  * and launches run on its own non-blocking streams, unordered with the
  * caller's: work the caller enqueued on raw or out must be complete before
  * the call.  Returns LPA_AGAIN if the admission queue (1024 frames) is full. */
+/* A frame none of the batch tile shapes (16x16, 32x8, 8x32, 64x4 output
+ * pixels) can stage is refused here with LPA_ERR_UNSUPPORTED; a frame that
+ * cannot fit the HBM budget beside what the context holds while no served
+ * frame is in flight finishes with LPA_ERR_OOM. */
 lpa_status lpa_submit(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
                       const lpa_output* out, int64_t arrival_ns, uint64_t* ticket);
-/* Non-blocking: LPA_NOT_READY until the frame is done; then its result.  A
- * ticket can be polled until the context is destroyed. */
+/* Non-blocking: LPA_NOT_READY until the frame is done; then its result,
+ * handed out once: the ticket is forgotten after that (a later poll returns
+ * LPA_ERR_INVALID_ARG), so the context keeps no record of collected frames. */
 lpa_status lpa_poll(lpa_ctx* ctx, uint64_t ticket, lpa_result* out);
 /* Block until every submitted frame is finished. */
 lpa_status lpa_drain(lpa_ctx* ctx);

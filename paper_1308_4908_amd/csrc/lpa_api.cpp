@@ -96,18 +96,18 @@ lpa_status validate_rig(const lpa_rig_desc* d) {
   return LPA_OK;
 }
 
-// Device plane of a sensor's calibration frames: per pixel (b_i, 1 / (g n a_i),
+// Device plane of a sensor's calibration frames: per pixel (b_i, a_i,
 // Var[r_i], saturation_i), the saturation -inf where the defect mask is set.
+// The frames' values are kept as given (the FP64 refit decodes with them).
 static std::vector<float4> pack_calib(const lpa_sensor_desc& S) {
   const lpa_calib& C = *S.calib;
   const int64_t n = (int64_t)S.width * S.height;
   std::vector<float4> out((size_t)n);
-  const double ge = S.gain * S.exposure;
   for (int64_t i = 0; i < n; ++i) {
     const double a = C.prnu ? C.prnu[i] : 1.0;
     float4 c;
     c.x = C.bias ? C.bias[i] : (float)S.black_level;
-    c.y = (float)(1.0 / (ge * a));
+    c.y = (float)a;
     c.z = C.read_var ? C.read_var[i] : (float)(S.read_sigma * S.read_sigma);
     c.w = C.saturation ? C.saturation[i] : (float)S.saturation;
     if (C.defect && C.defect[i]) c.w = -INFINITY;
@@ -139,6 +139,7 @@ lpa_status resolve_params(const lpa_params* p, Resolved* r) {
     return set_error(LPA_ERR_INVALID_ARG, "storage %d invalid", p->storage);
   if (!std::isfinite(p->tau_inv) || !std::isfinite(p->tau_fp64))
     return set_error(LPA_ERR_INVALID_ARG, "thresholds not finite");
+  if (!std::isfinite(p->value_tol)) return set_error(LPA_ERR_INVALID_ARG, "value_tol not finite");
   r->p = *p;
   r->tau_inv = p->tau_inv > 0 ? p->tau_inv : 1e-5;
   r->tau_fp64 = p->tau_fp64 > 0 ? p->tau_fp64 : 1e-3;
@@ -150,8 +151,10 @@ lpa_status resolve_params(const lpa_params* p, Resolved* r) {
     const double vals[] = {p->alpha, p->lambda1, p->lambda2, p->grad_radius, p->grad_h, p->max_stretch};
     for (double v : vals)
       if (!std::isfinite(v)) return set_error(LPA_ERR_INVALID_ARG, "adaptive parameters not finite");
-    if (!(p->alpha >= 0) || !(p->lambda1 >= 0) || !(p->lambda2 >= 0))
-      return set_error(LPA_ERR_INVALID_ARG, "alpha, lambda1 and lambda2 must be >= 0");
+    // lambda1 > 0: with no gradient in the analysis window s1 = s2 = 0 and the
+    // elongation (s1 + lambda1) / (s2 + lambda1) would be 0/0
+    if (!(p->alpha >= 0) || !(p->lambda1 > 0) || !(p->lambda2 >= 0))
+      return set_error(LPA_ERR_INVALID_ARG, "alpha and lambda2 must be >= 0, lambda1 > 0");
     if (p->grad_order < 0 || p->grad_order > 2)
       return set_error(LPA_ERR_INVALID_ARG, "grad_order %d invalid", p->grad_order);
     if (p->grad_halfwin < 0 || p->grad_halfwin > 16)
@@ -221,7 +224,16 @@ void rig_constants(const lpa_sensor_desc& S, SensorK* k) {
   k->read_var = (float)(S.read_sigma * S.read_sigma);
   k->black = (float)S.black_level;
   k->sat = (float)S.saturation;
+  k->gain64 = S.gain;
+  k->ge64 = ge;
+  k->black64 = S.black_level;
+  k->read_var64 = S.read_sigma * S.read_sigma;
+  k->sat64 = S.saturation;
   k->norm_decode = std::ldexp(1.0f, S.bit_depth);
+  // FP16 storage offset: 2^(bits-1) makes every raw value of up to 12 bits
+  // exact in FP16 (integers of magnitude <= 2048); deeper ADCs store the
+  // value above the black level (exact up to 2048 DN above it)
+  k->norm_offset = S.bit_depth <= 12 ? std::ldexp(1.0f, S.bit_depth - 1) : (float)S.black_level;
   k->width = S.width;
   k->height = S.height;
   for (int c = 0; c < 3; ++c) {
@@ -243,10 +255,13 @@ void rig_constants(const lpa_sensor_desc& S, SensorK* k) {
 // limit.
 constexpr int64_t kStaticLdsReserve = 256;
 
+// Default accuracy target of the output values (lpa_params.value_tol = 0).
+constexpr double kDefaultValueTol = 1e-4;
+
 // Fill the launch-dependent parts of a descriptor.  Returns false if the
 // LDS footprint of the requested tile does not fit.
-lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output* out, int src_kind,
-                        const void* const* srcs, const int64_t* pitches, int tile_w, int tile_h,
+lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_frame* frame, const lpa_output* out,
+                        int src_kind, const void* const* srcs, const int64_t* pitches, int tile_w, int tile_h,
                         LaunchK* K) {
   const lpa_params& p = R.p;
   std::memset(K, 0, sizeof(*K));
@@ -267,12 +282,21 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output*
   K->tau_inv = (float)R.tau_inv;
   K->tau_fp64 = (float)R.tau_fp64;
   K->use_fp64 = (p.flags & LPA_FLAG_NO_FP64_FALLBACK) ? 0 : 1;
+  // FP64 values where the FP32 moments' rounding bound exceeds the target:
+  // 16 u S > value_tol * max(|C0|, floor), u = 2^-24 (the factor 16 covers the
+  // rounding of the products and partial sums each moment term goes through)
+  double ge_max = 0;
+  for (int s = 0; s < rig->n; ++s) ge_max = std::max(ge_max, rig->desc[s].gain * rig->desc[s].exposure);
+  K->value_floor = (float)(1.0 / ge_max);
+  const double vtol = p.value_tol == 0 ? kDefaultValueTol : p.value_tol;
+  K->risk_max = (vtol < 0 || !K->use_fp64) ? INFINITY : (float)(vtol / (16.0 * std::ldexp(1.0, -24)));
   K->rgb = out->rgb;
   K->rgb_pitch = out->row_pitch_bytes;
   K->map = out->scale_map;
   K->map_pitch = out->scale_map_pitch;
   K->sd = out->sd_map;
   K->sd_pitch = out->sd_map_pitch;
+  K->frame_stats = out->stats;
   K->need_var = (p.n_scales > 1 || out->sd_map) ? 1 : 0;
 
   for (int m = 0; m < p.n_scales; ++m) {
@@ -287,6 +311,7 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output*
       const double reach = (double)(float)cs * r * (1 + 1e-4);
       K->sc[m].reach2[cls] = (float)(reach * reach);
       K->sc[m].e_edge[cls] = (float)std::exp(-r * r / h);
+      K->sc[m].h[cls] = h;
     }
   }
   int lds = 0;
@@ -296,6 +321,9 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output*
     S = rig->k[s];
     S.src = srcs[s];
     S.pitch = pitches[s];
+    S.raw = frame->raw[s];
+    S.raw_pitch = frame->row_pitch_bytes[s];
+    S.raw_f32 = frame->dtype == LPA_DTYPE_F32 ? 1 : 0;
     double wmx = 0, wmy = 0;
     for (int cls = 0; cls < 2; ++cls) {
       for (int m = 0; m < p.n_scales; ++m) {
@@ -343,14 +371,14 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output*
 // Tile shapes tried in order (largest first) when a tile's LDS does not fit.
 static const int kTileShapes[][2] = {{16, 16}, {16, 8}, {8, 8}, {8, 4}, {4, 4}};
 
-lpa_status build_launch_fit(const lpa_rig* rig, const Resolved& R, const lpa_output* out, int src_kind,
-                            const void* const* srcs, const int64_t* pitches, int pref_w, int pref_h,
+lpa_status build_launch_fit(const lpa_rig* rig, const Resolved& R, const lpa_frame* frame, const lpa_output* out,
+                            int src_kind, const void* const* srcs, const int64_t* pitches, int pref_w, int pref_h,
                             LaunchK* K) {
-  lpa_status st = build_launch(rig, R, out, src_kind, srcs, pitches, pref_w, pref_h, K);
+  lpa_status st = build_launch(rig, R, frame, out, src_kind, srcs, pitches, pref_w, pref_h, K);
   if (st != LPA_ERR_UNSUPPORTED) return st;
   for (const auto& t : kTileShapes) {
     if (t[0] * t[1] >= pref_w * pref_h) continue;
-    st = build_launch(rig, R, out, src_kind, srcs, pitches, t[0], t[1], K);
+    st = build_launch(rig, R, frame, out, src_kind, srcs, pitches, t[0], t[1], K);
     if (st != LPA_ERR_UNSUPPORTED) return st;
   }
   return st;
@@ -407,6 +435,52 @@ lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_
   return LPA_OK;
 }
 
+// Per-tile count buffer for a frame whose output asks for the FP64-valued and
+// no-data counts (lpa_output.stats); stats_end sums it into the caller's
+// counters after the fit and frees it.
+static lpa_status stats_begin(lpa_ctx* ctx, const lpa_output* out, LaunchK* K, hipStream_t hs, void** buf,
+                              size_t* bytes) {
+  *buf = nullptr;
+  *bytes = 0;
+  if (!out->stats) return LPA_OK;
+  *bytes = (size_t)K->tiles_x * K->tiles_y * 2 * sizeof(uint32_t);
+  lpa_status st = alloc_async(ctx, *bytes, hs, buf);
+  if (st == LPA_OK) K->tile_stats = static_cast<uint32_t*>(*buf);
+  return st;
+}
+
+static lpa_status stats_end(lpa_ctx* ctx, const lpa_output* out, const LaunchK& K, hipStream_t hs, void* buf,
+                            size_t bytes, lpa_status st) {
+  if (st == LPA_OK && buf &&
+      lpa_k_stats_sum(K.tile_stats, (int64_t)K.tiles_x * K.tiles_y, out->stats, hs) != 0)
+    st = device_error(ctx, hipGetLastError(), "count reduction");
+  free_async(ctx, buf, bytes, hs);
+  return st;
+}
+
+// The FP64 refit of the outputs a fit marks: a map of marks (3 bytes per
+// output pixel, stream-ordered scratch) that the fit writes and refit_end's
+// launch reads.  Launches whose accuracy target is off need neither.
+static lpa_status refit_begin(lpa_ctx* ctx, LaunchK* K, hipStream_t hs, void** buf, size_t* bytes) {
+  *buf = nullptr;
+  *bytes = 0;
+  if (!std::isfinite(K->risk_max)) return LPA_OK;
+  *bytes = (size_t)K->out_w * K->out_h * 3;
+  lpa_status st = alloc_async(ctx, *bytes, hs, buf);
+  if (st == LPA_OK) {
+    K->refit_map = static_cast<uint8_t*>(*buf);
+    K->refit_pitch = (int64_t)3 * K->out_w;
+  }
+  return st;
+}
+
+static lpa_status refit_end(lpa_ctx* ctx, const LaunchK& K, hipStream_t hs, void* buf, size_t bytes,
+                            lpa_status st) {
+  if (st == LPA_OK && buf && lpa_k_refit(&K, hs) != 0) st = device_error(ctx, hipGetLastError(), "refit launch");
+  free_async(ctx, buf, bytes, hs);
+  return st;
+}
+
 // Adaptive anisotropic LPA with colour-channel correlation (Sec. 5.4, 5.5):
 // gradient pass (G channel, isotropic), steering pass, steered fit of R, G, B.
 // Every descriptor is built and checked before anything is enqueued.
@@ -444,12 +518,12 @@ static lpa_status calpa_impl(lpa_rig* rig, const lpa_frame* frame, const Resolve
   og.rgb = out->rgb;
   og.row_pitch_bytes = out->row_pitch_bytes;
   LaunchK Kg, Ks;
-  lpa_status st = build_launch_fit(rig, Rg, &og, src_kind, srcs, pitches, 16, 16, &Kg);
+  lpa_status st = build_launch_fit(rig, Rg, frame, &og, src_kind, srcs, pitches, 16, 16, &Kg);
   if (st != LPA_OK) return st;
   // steered fit: boxes cover the ellipse, within max_stretch * r of the pixel
   Resolved Rs = R;
   Rs.box_stretch = R.max_stretch;
-  if ((st = build_launch_fit(rig, Rs, out, src_kind, srcs, pitches, 16, 16, &Ks)) != LPA_OK) return st;
+  if ((st = build_launch_fit(rig, Rs, frame, out, src_kind, srcs, pitches, 16, 16, &Ks)) != LPA_OK) return st;
 
   const int W = R.p.out_w, H = R.p.out_h;
   void* gbuf = nullptr;
@@ -504,7 +578,14 @@ static lpa_status calpa_impl(lpa_rig* rig, const lpa_frame* frame, const Resolve
   }
   Ks.steer = sptr;
   Ks.steer_pitch = spitch;
+  void* cbuf = nullptr;
+  void* rbuf = nullptr;
+  size_t cbytes = 0, rbytes = 0;
+  if (st == LPA_OK) st = stats_begin(ctx, out, &Ks, hs, &cbuf, &cbytes);
+  if (st == LPA_OK) st = refit_begin(ctx, &Ks, hs, &rbuf, &rbytes);
   if (st == LPA_OK && lpa_k_fit_steered(&Ks, hs) != 0) st = device_error(ctx, hipGetLastError(), "steered fit launch");
+  st = refit_end(ctx, Ks, hs, rbuf, rbytes, st);
+  st = stats_end(ctx, out, Ks, hs, cbuf, cbytes, st);
   for (int s = 0; s < rig->n; ++s) free_async(ctx, planes[s], plane_bytes[s], hs);
   free_async(ctx, gbuf, gbytes, hs);
   free_async(ctx, sbuf, sbytes, hs);
@@ -564,8 +645,8 @@ lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_para
   // The pre-computed-weight kernel needs one parity class per wave: 16 x 16.
   // The other forms fall back to smaller tiles when wide windows over many
   // sensors overflow the LDS of the preferred one (16 x 16 for the plain form).
-  st = stencil ? build_launch(rig, R, out, src_kind, srcs, pitches, 16, 16, &K)
-               : build_launch_fit(rig, R, out, src_kind, srcs, pitches, tw, th, &K);
+  st = stencil ? build_launch(rig, R, frame, out, src_kind, srcs, pitches, 16, 16, &K)
+               : build_launch_fit(rig, R, frame, out, src_kind, srcs, pitches, tw, th, &K);
   if (st != LPA_OK) return st;
   K.occupancy = tc.occupancy;
   if (stencil) {
@@ -581,8 +662,15 @@ lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_para
         K.s[s].pitch = pitches[s];
       }
   }
+  void* cbuf = nullptr;
+  void* rbuf = nullptr;
+  size_t cbytes = 0, rbytes = 0;
+  if (st == LPA_OK) st = stats_begin(ctx, out, &K, hs, &cbuf, &cbytes);
+  if (st == LPA_OK) st = refit_begin(ctx, &K, hs, &rbuf, &rbytes);
   if (st == LPA_OK && (stencil ? lpa_k_fit_stencil(&K, hs) : lpa_k_fit(&K, hs)) != 0)
     st = device_error(ctx, hipGetLastError(), "fit launch");
+  st = refit_end(ctx, K, hs, rbuf, rbytes, st);
+  st = stats_end(ctx, out, K, hs, cbuf, cbytes, st);
   for (int s = 0; s < rig->n; ++s) free_async(ctx, planes[s], plane_bytes[s], hs);
   return st;
 }

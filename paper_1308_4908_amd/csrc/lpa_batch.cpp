@@ -25,9 +25,24 @@ TuneKey Tuner::key_of(const lpa_rig* rig, const Resolved& R, int src_kind) {
   return k;
 }
 
+// 256-lane tile shapes a batched frame may take (a batch needs one lane count).
+static const int kBatchTiles[][2] = {{16, 16}, {32, 8}, {8, 32}, {64, 4}};
+
 static int src_kind_of(const lpa_params& p, const lpa_frame& f) {
   if (p.storage == LPA_STORE_FUSED) return f.dtype == LPA_DTYPE_U16 ? SRC_RAW_U16 : SRC_RAW_F32;
   return p.storage == LPA_STORE_FP16 ? SRC_PLANE_F16 : SRC_PLANE_F32;
+}
+
+lpa_status check_batchable(const lpa_rig* rig, const Resolved& R, const lpa_frame* frame, const lpa_output* out) {
+  const void* srcs[LPA_MAX_SENSORS] = {nullptr};
+  int64_t pitches[LPA_MAX_SENSORS] = {0};
+  LaunchK K;
+  lpa_status st = LPA_ERR_UNSUPPORTED;
+  for (const auto& t : kBatchTiles) {
+    st = build_launch(rig, R, frame, out, src_kind_of(R.p, *frame), srcs, pitches, t[0], t[1], &K);
+    if (st != LPA_ERR_UNSUPPORTED) break;
+  }
+  return st;
 }
 
 lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_frame* frames,
@@ -61,10 +76,10 @@ lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_f
     }
     const TuneChoice tc = ctx->tuner.choose(Tuner::key_of(rigs[i], Rs[i], sk));
     int tw = tc.tile_w, th = tc.tile_h;
-    lpa_status st = build_launch(rigs[i], Rs[i], &outs[i], sk, srcs, pitches, tw, th, &(*ks)[i]);
+    lpa_status st = build_launch(rigs[i], Rs[i], &frames[i], &outs[i], sk, srcs, pitches, tw, th, &(*ks)[i]);
     if (st == LPA_ERR_UNSUPPORTED && tw * th == 256)
-      for (const int* t : {(const int[]){16, 16}, (const int[]){32, 8}, (const int[]){64, 4}}) {
-        st = build_launch(rigs[i], Rs[i], &outs[i], sk, srcs, pitches, t[0], t[1], &(*ks)[i]);
+      for (const auto& t : kBatchTiles) {
+        st = build_launch(rigs[i], Rs[i], &frames[i], &outs[i], sk, srcs, pitches, t[0], t[1], &(*ks)[i]);
         if (st != LPA_ERR_UNSUPPORTED) break;
       }
     if (st != LPA_OK) return set_error(st, "frame %d: %s", i, g_last_error);
@@ -89,6 +104,9 @@ lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_f
   return LPA_OK;
 }
 
+lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, int block, int lds, int grid,
+                        int64_t total, hipStream_t stream);
+
 static void slot_release(BatchSlot& sl) {
   if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
   if (sl.h_buf) (void)hipHostFree(sl.h_buf);
@@ -99,18 +117,66 @@ static void slot_release(BatchSlot& sl) {
   sl.cap = 0;
 }
 
-lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, hipStream_t stream) {
-  const int n = (int)ks.size();
+lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks_in, int src_kind, hipStream_t stream,
+                        bool charge) {
+  std::vector<LaunchK> ks = ks_in;
   int block = ks[0].tile_w * ks[0].tile_h;
   int lds = 0;
   int64_t total = 0;
   for (const LaunchK& K : ks) {
     if (K.tile_w * K.tile_h != block) return set_error(LPA_ERR_INTERNAL, "batch tiles differ in lane count");
+    for (int s = 0; s < K.n_sensors; ++s)
+      if (!K.s[s].raw) return set_error(LPA_ERR_INTERNAL, "batch frame without raw planes");
     lds = std::max(lds, K.lds_floats2);
     total += (int64_t)K.tiles_x * K.tiles_y;
   }
   if (total > (int64_t)INT32_MAX) return set_error(LPA_ERR_UNSUPPORTED, "batch exceeds 2^31 tiles");
   const int grid = (int)std::min<int64_t>(total, (int64_t)ctx->n_cu * 4);
+  // per-tile counts for the frames whose outputs ask for them, and the refit
+  // marks (3 bytes per output pixel) of the frames with an accuracy target
+  void* cbuf = nullptr;
+  void* rbuf = nullptr;
+  size_t cbytes = 0, rbytes = 0;
+  bool counts = false;
+  for (const LaunchK& K : ks) {
+    counts = counts || K.frame_stats;
+    if (std::isfinite(K.risk_max)) rbytes += (size_t)K.out_w * K.out_h * 3;
+  }
+  if (counts) {
+    cbytes = (size_t)total * 2 * sizeof(uint32_t);
+    lpa_status cs = alloc_async(ctx, cbytes, stream, &cbuf, charge);
+    if (cs != LPA_OK) return cs;
+    int64_t at = 0;
+    for (LaunchK& K : ks) {
+      if (K.frame_stats) K.tile_stats = static_cast<uint32_t*>(cbuf) + 2 * at;
+      at += (int64_t)K.tiles_x * K.tiles_y;
+    }
+  }
+  if (rbytes) {
+    lpa_status rs = alloc_async(ctx, rbytes, stream, &rbuf, charge);
+    if (rs != LPA_OK) {
+      free_async(ctx, cbuf, cbytes, stream, charge);
+      return rs;
+    }
+    size_t at = 0;
+    for (LaunchK& K : ks) {
+      if (!std::isfinite(K.risk_max)) continue;
+      K.refit_map = static_cast<uint8_t*>(rbuf) + at;
+      K.refit_pitch = (int64_t)3 * K.out_w;
+      at += (size_t)K.out_w * K.out_h * 3;
+    }
+  }
+  lpa_status st = launch_table(ctx, ks, src_kind, block, lds, grid, total, stream);
+  free_async(ctx, rbuf, rbytes, stream, charge);
+  free_async(ctx, cbuf, cbytes, stream, charge);
+  return st;
+}
+
+// Copy the table into a slot and replay (or capture) its graph: the table
+// copy, the queue reset, the persistent kernel and the count reduction.
+lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, int block, int lds, int grid,
+                        int64_t total, hipStream_t stream) {
+  const int n = (int)ks.size();
 
   std::lock_guard<std::mutex> g(ctx->batch_mu);
   BatchSlot& sl = ctx->slots[ctx->next_slot];
@@ -159,6 +225,10 @@ lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
     (void)lpa_k_fit_batch(reinterpret_cast<const BatchHeader*>(d), reinterpret_cast<const LaunchK*>(d + L.frames_off),
                           reinterpret_cast<const int64_t*>(d + L.first_off), q, src_kind, block, lds, grid,
                           ctx->capture_stream);
+    (void)lpa_k_refit_batch(reinterpret_cast<const BatchHeader*>(d), reinterpret_cast<const LaunchK*>(d + L.frames_off),
+                            reinterpret_cast<const int64_t*>(d + L.first_off), ctx->n_cu * 8, ctx->capture_stream);
+    (void)lpa_k_stats_frames(reinterpret_cast<const BatchHeader*>(d), reinterpret_cast<const LaunchK*>(d + L.frames_off),
+                             sl.cap, ctx->capture_stream);
     if ((e = hipStreamEndCapture(ctx->capture_stream, &graph)) != hipSuccess) return device_error(ctx, e, "end capture");
     e = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);

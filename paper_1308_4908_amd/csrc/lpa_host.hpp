@@ -166,11 +166,14 @@ lpa_status check_ctx(lpa_ctx* ctx);
 lpa_status resolve_params(const lpa_params* p, Resolved* r);
 lpa_status validate_frame(const lpa_rig* rig, const lpa_frame* f, bool need_device);
 lpa_status validate_output(const lpa_params* p, const lpa_output* o);
-lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_output* out, int src_kind,
-                        const void* const* srcs, const int64_t* pitches, int tile_w, int tile_h,
+// A launch descriptor for `frame` (its raw planes are what the FP64 refit
+// reads; srcs / pitches are where the fit reads samples: the raw planes or
+// pre-pass planes, null until the pre-pass has run).
+lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_frame* frame, const lpa_output* out,
+                        int src_kind, const void* const* srcs, const int64_t* pitches, int tile_w, int tile_h,
                         LaunchK* K);
-lpa_status build_launch_fit(const lpa_rig* rig, const Resolved& R, const lpa_output* out, int src_kind,
-                            const void* const* srcs, const int64_t* pitches, int pref_w, int pref_h,
+lpa_status build_launch_fit(const lpa_rig* rig, const Resolved& R, const lpa_frame* frame, const lpa_output* out,
+                            int src_kind, const void* const* srcs, const int64_t* pitches, int pref_w, int pref_h,
                             LaunchK* K);
 // Stream-ordered scratch; `charge` counts it against the context's HBM budget
 // (the serving scheduler charges a frame's whole footprint at admission).
@@ -191,7 +194,10 @@ void ctx_shutdown_runtime(lpa_ctx* ctx);
 
 // Launch a prepared batch (descriptors already built, planes already made) on
 // `stream` through a slot's captured graph.  Thread-safe.
-lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, hipStream_t stream);
+// Frames whose outputs ask for counts get a per-tile count buffer (8 bytes per
+// tile) for the launch; `charge` counts it against the budget.
+lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, hipStream_t stream,
+                        bool charge = true);
 // Build descriptors for a list of frames (validating each) and run the
 // pre-pass where the storage form needs one; plane allocations are returned
 // for the caller to free (stream-ordered) after the launch.
@@ -203,6 +209,9 @@ lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_f
                           const lpa_params* params, const lpa_output* outs, hipStream_t stream,
                           std::vector<LaunchK>* ks, int* src_kind, std::vector<PlaneAlloc>* planes,
                           bool charge = true);
+// Whether a frame can join a batch: some 256-lane tile shape stages its
+// windows (LPA_ERR_UNSUPPORTED with the reason otherwise).
+lpa_status check_batchable(const lpa_rig* rig, const Resolved& R, const lpa_frame* frame, const lpa_output* out);
 lpa_status serve_init(lpa_ctx* ctx);
 void serve_shutdown(lpa_ctx* ctx);
 

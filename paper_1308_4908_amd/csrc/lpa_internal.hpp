@@ -31,7 +31,8 @@ struct SensorK {
   float read_var;       // sigma_r^2 [DN^2]
   float black;          // b [DN]
   float sat;            // saturation [DN]
-  float norm_decode;    // 2^bit_depth (FP16 plane value -> y - b)
+  float norm_decode;    // 2^bit_depth: FP16 plane value v -> y = v 2^bits + norm_offset
+  float norm_offset;    // 2^(bit_depth - 1) up to 12 bits (lossless), else the black level
   int32_t width, height;
   int32_t reg_w, reg_h; // LDS region bound (samples) for the launch's tile shape
   int32_t lds_off;      // region offset in the LDS sample array (float2 units)
@@ -41,8 +42,17 @@ struct SensorK {
   int8_t nbox[2][kMaxScales][2]; // box size (sub-lattice points) [class][scale][x|y]
   int8_t pad_[5];
   // per-pixel calibration (row-major width*height), or null for the scalars:
-  // (b_i, 1 / (g n a_i), Var[r_i], saturation_i), saturation -inf for defects
+  // (b_i, a_i, Var[r_i], saturation_i), saturation -inf for defects
   const float4* calib;
+  // The frame's raw plane (also for the pre-pass forms) and the noise model in
+  // FP64, read by the FP64 refit of outputs whose FP32 value is not accurate
+  // enough.
+  const void* raw;
+  int64_t raw_pitch;    // bytes
+  int32_t raw_f32;      // raw samples are float DN (else uint16)
+  int32_t pad2_;
+  double gain64, ge64;  // g, g n
+  double black64, read_var64, sat64;
 };
 
 // Per-scale constants, per channel class (0: R and B, 1: G).
@@ -52,6 +62,7 @@ struct ScaleK {
   float coord_scale[2]; // s = sqrt(log2(e) / h'): exp(-|d|^2 / h') = exp2(-|s d|^2)
   float reach2[2];    // (s r' (1 + 1e-4))^2: samples at or beyond it have exactly zero weight
   float e_edge[2];    // exp(-r'^2 / h'): subtracted so the window vanishes at r'
+  double h[2];        // h' = h * kappa_class^2 (FP64 refit)
 };
 
 // Pre-computed window weights (rigs whose sensor maps and output map are
@@ -90,7 +101,23 @@ struct LaunchK {
   int32_t lds_floats2;      // float2 elements of LDS this launch uses
   int32_t need_var;         // estimator variance needed (several radii or an sd map)
   int32_t occupancy;        // 0: default register budget; 4: compiled for 4 waves/SIMD (order 2)
+  // Output values are recomputed from FP64 moments where the FP32 moments'
+  // rounding could move them by more than the target: when the bound S on
+  // |dC0| per unit relative rounding of the moment terms exceeds
+  // risk_max * max(|C0|, value_floor) (risk_max = +inf: never).
+  float risk_max;
+  float value_floor;        // one DN of the most exposed sensor, in radiance units
   int32_t pad2_;
+  // optional per-tile counts (2 x uint32 per tile: outputs whose value came
+  // from an FP64 solve, outputs with no valid fit), indexed by the frame's
+  // tile number; null: not counted
+  uint32_t* tile_stats;
+  uint64_t* frame_stats;    // where the batch's count reduction writes this frame's sums (or null)
+  // per output (pixel x channel) byte: 0x80 | order << 4 | radius index where
+  // the output is to be refitted in FP64, else 0; written by the fit, read by
+  // the refit launch (null: no refit)
+  uint8_t* refit_map;
+  int64_t refit_pitch;      // bytes
   float* rgb;
   int64_t rgb_pitch;        // bytes
   uint8_t* map;
@@ -169,6 +196,18 @@ int lpa_k_steer(const lpa::SteerArgs* a, void* stream);
 int lpa_k_fit_stencil(const lpa::LaunchK* k, void* stream);
 // Fit with per-pixel steered windows read from K.steer.
 int lpa_k_fit_steered(const lpa::LaunchK* k, void* stream);
+// FP64 refit of the outputs a fit launch marked in K.refit_map (one launch
+// over the frame's tiles, after the fit on the same stream).
+int lpa_k_refit(const lpa::LaunchK* k, void* stream);
+// The same for a batch table (after the persistent fit; grid workgroups loop
+// over the batch's tiles).
+int lpa_k_refit_batch(const lpa::BatchHeader* hdr, const lpa::LaunchK* frames, const int64_t* first_tile,
+                      int32_t grid, void* stream);
 // Zero n ints with a small kernel (graph-safe replacement for a memset).
 int lpa_k_zero_i32(int32_t* p, int32_t n, void* stream);
+// Sum a frame's per-tile counts (n_tiles pairs) into out[0], out[1].
+int lpa_k_stats_sum(const uint32_t* tile_stats, int64_t n_tiles, uint64_t* out, void* stream);
+// The same for every frame of a batch table: workgroup f handles frame f
+// (f < hdr->n_frames) if its descriptor carries tile_stats and frame_stats.
+int lpa_k_stats_frames(const lpa::BatchHeader* hdr, const lpa::LaunchK* frames, int32_t grid, void* stream);
 }

@@ -59,6 +59,7 @@ struct Acc {
   float m[n_mom<ORDER>()];            // sum w * monomial
   float b[n_basis<ORDER>()];          // sum w * f * phi
   float B[ICI ? n_mom<ORDER>() : 1];  // sum K w * monomial (variance of C0)
+  float f2;                           // sum w f^2 (bounds the rounding error of C0)
 };
 
 template <int ORDER, bool ICI>
@@ -69,6 +70,7 @@ __device__ __forceinline__ void acc_zero(Acc<ORDER, ICI>& a) {
   for (int k = 0; k < n_basis<ORDER>(); ++k) a.b[k] = 0.f;
 #pragma unroll
   for (int k = 0; k < (ICI ? n_mom<ORDER>() : 1); ++k) a.B[k] = 0.f;
+  a.f2 = 0.f;
 }
 
 // One sample: scaled offset (dx, dy), radiance f, inverse variance iv.  The
@@ -120,8 +122,11 @@ __device__ __forceinline__ bool acc_sample(Acc<ORDER, ICI>& a, float dx, float d
       a.m[12] = __builtin_fmaf(wxx, y2, a.m[12]);
       a.m[13] = __builtin_fmaf(wxy, y2, a.m[13]);
       a.m[14] = __builtin_fmaf(wyy, y2, a.m[14]);
+      const float wf = w * f;
+      a.b[0] += wf;
+      a.f2 = __builtin_fmaf(wf, f, a.f2);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) a.b[k] = __builtin_fmaf(f, p[k], a.b[k]);
+      for (int k = 1; k < 6; ++k) a.b[k] = __builtin_fmaf(f, p[k], a.b[k]);
       if constexpr (ICI) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) a.B[k] = __builtin_fmaf(kw, p[k], a.B[k]);
@@ -152,6 +157,7 @@ __device__ __forceinline__ bool acc_sample(Acc<ORDER, ICI>& a, float dx, float d
 #pragma unroll
       for (int k = 1; k < n_mom<ORDER>(); ++k) a.m[k] = __builtin_fmaf(w, mono[k], a.m[k]);
       a.b[0] += wf;
+      a.f2 = __builtin_fmaf(wf, f, a.f2);
 #pragma unroll
       for (int k = 1; k < n_basis<ORDER>(); ++k) a.b[k] = __builtin_fmaf(wf, mono[k], a.b[k]);
       if constexpr (ICI) {
@@ -183,6 +189,11 @@ struct Fits {
   T rho[ORDER + 1];
   bool ok[ORDER + 1];
   T g[ORDER + 1][n_basis<ORDER>()];  // A^-1 e0 of each order (C0 = g . b)
+  // Bound on |dC0| per unit relative rounding of every moment term:
+  // sum_i |g_i| sqrt(A_ii) (sqrt(F2) + sum_j sqrt(A_jj) |C_j|), F2 = sum w f^2.
+  // By Cauchy-Schwarz it is at least the componentwise condition
+  // |g|'|b|abs + |g|'|A|abs|C| (|.|abs: sums of absolute terms).
+  T s[ORDER + 1];
 };
 
 template <typename T>
@@ -192,9 +203,9 @@ __device__ __forceinline__ float rcp_t<float>(float x) { return __builtin_amdgcn
 template <>
 __device__ __forceinline__ double rcp_t<double>(double x) { return 1.0 / x; }
 
-template <typename T, int ORDER, bool ICI>
+template <typename T, int ORDER, bool ICI, bool BOUND = false>
 __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T tau, bool lower,
-                                           Fits<T, ORDER>& out) {
+                                           Fits<T, ORDER>& out, T f2 = T(0)) {
   constexpr int NB = n_basis<ORDER>();
   T L[NB][NB], U[NB][NB];  // U[i][k] = L[i][k] D[k]
   T D[NB], iD[NB], req[NB];
@@ -228,6 +239,18 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T
     for (int k = 0; k < i; ++k) t -= L[i][k] * z[k];
     z[i] = t;
   }
+  // forward substitution of b and the diagonal's square roots (bound only)
+  T zb[NB], sq[NB];
+  if constexpr (BOUND) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      T t = b[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) t -= L[i][k] * zb[k];
+      zb[i] = t;
+      sq[i] = __builtin_amdgcn_sqrtf(fmaxf(m[aidx(i, i)], T(0)));
+    }
+  }
   T rho = T(3.0e38);
   bool diag_all = true;
 #pragma unroll
@@ -240,7 +263,7 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T
       diag_all = diag_all && dok[i];
     }
     if (o < ORDER && !lower) {  // lower orders not needed (wave-uniform)
-      out.y[o] = out.v[o] = out.rho[o] = T(0);
+      out.y[o] = out.v[o] = out.rho[o] = out.s[o] = T(0);
       out.ok[o] = false;
 #pragma unroll
       for (int i = 0; i < NB; ++i) out.g[o][i] = T(0);
@@ -280,6 +303,28 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T
     }
     out.y[o] = y;
     out.v[o] = v;
+    out.s[o] = T(0);
+    // (the lower orders, kept for fallback, go without: a fallback output is
+    // always recomputed in FP64)
+    if constexpr (BOUND) if (o == ORDER) {
+      T c[NB];
+      T sg = T(0), scs = T(0);
+#pragma unroll
+      for (int i = NB - 1; i >= 0; --i) {
+        if (i < no) {
+          T t = zb[i] * iD[i];
+#pragma unroll
+          for (int k = i + 1; k < NB; ++k)
+            if (k < no) t -= L[k][i] * c[k];
+          c[i] = t;
+          sg = __builtin_fmaf(fabsf(g[i]), sq[i], sg);
+          scs = __builtin_fmaf(fabsf(t), sq[i], scs);
+        } else {
+          c[i] = T(0);
+        }
+      }
+      out.s[o] = sg * (__builtin_amdgcn_sqrtf(fmaxf(f2, T(0))) + scs);
+    }
     out.rho[o] = (diag_all && rho > T(0)) ? rho : T(0);
     // Provisional: the caller also requires >= no samples where rho alone
     // does not certify it.
@@ -287,104 +332,164 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T
   }
 }
 
-// Equilibrated pivots of the leading blocks (orders 0..ORDER), in FP64, of a
-// normal matrix re-accumulated in FP64.  Where a pivot is small, the pivots
-// after it carry the rounding of FP32 moments amplified by its inverse: the
-// samples of a support lying on one line (one sensor column, say) give an
-// exactly singular matrix whose FP32 moments can look regular, with a pivot
-// far above tau.  The FP32 factorization decides every fit whose pivots all
-// stay above kPivotCertifiesN (rounding cannot bring them to tau); the
-// others are decided on these pivots.
+// ---------------------------------------------------------------------------
+// FP64 moments and solve.  In HDR windows C0 is often a small difference of
+// large terms (a dark pixel beside a bright edge, an exactly determined fit),
+// and rounding each FP32 product and partial sum of the moments on its own
+// leaves A and b mutually inconsistent by ~u relative, which that cancellation
+// multiplies.  Rounding only the inputs of every moment -- offsets, window
+// weight, inverse variance, radiance -- does far less harm: it is the exact fit
+// of a slightly moved sample set.  The FP64 pass of ill-conditioned fits
+// (validity, and the values and variances the ICI steps compare) therefore
+// keeps the main pass's FP32 offsets and weights and forms products and sums
+// in FP64; output values that need more are refitted from the raw frame
+// (refit_kernel below).
+// ---------------------------------------------------------------------------
 template <int ORDER>
-__device__ __forceinline__ void pivots_fp64(const double* m, double* rho_o) {
-  constexpr int NB = n_basis<ORDER>();
+struct Acc64 {
+  double m[n_mom<ORDER>()];
+  double b[n_basis<ORDER>()];
+};
+
+template <int ORDER>
+__device__ __forceinline__ void acc64_zero(Acc64<ORDER>& a) {
+#pragma unroll
+  for (int k = 0; k < n_mom<ORDER>(); ++k) a.m[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < n_basis<ORDER>(); ++k) a.b[k] = 0.0;
+}
+
+// One sample of weight w.  `hi` (wave-uniform) adds the degree-3 and 4
+// moments and b's quadratic terms that an order-2 fit needs; without it only
+// the order <= 1 sums are formed.
+template <int ORDER, bool HAS_B = true>
+__device__ __forceinline__ void acc64_sample(Acc64<ORDER>& a, float dx, float dy, float f, float w, bool hi) {
+  const double wd = w, fd = f;
+  a.m[0] += wd;
+  if constexpr (HAS_B) a.b[0] = __builtin_fma(wd, fd, a.b[0]);
+  if constexpr (ORDER >= 1) {
+    const double x = dx, y = dy;
+    const double wx = wd * x, wy = wd * y;
+    const double wxx = wx * x, wxy = wx * y, wyy = wy * y;
+    a.m[1] += wx;
+    a.m[2] += wy;
+    a.m[3] += wxx;
+    a.m[4] += wxy;
+    a.m[5] += wyy;
+    if constexpr (HAS_B) {
+      a.b[1] = __builtin_fma(fd, wx, a.b[1]);
+      a.b[2] = __builtin_fma(fd, wy, a.b[2]);
+    }
+    if constexpr (ORDER >= 2) {
+      if (hi) {
+        const double xx = x * x, yy = y * y;
+        a.m[6] = __builtin_fma(wxx, x, a.m[6]);
+        a.m[7] = __builtin_fma(wxx, y, a.m[7]);
+        a.m[8] = __builtin_fma(wyy, x, a.m[8]);
+        a.m[9] = __builtin_fma(wyy, y, a.m[9]);
+        a.m[10] = __builtin_fma(wxx, xx, a.m[10]);
+        a.m[11] = __builtin_fma(wxy, xx, a.m[11]);
+        a.m[12] = __builtin_fma(wxx, yy, a.m[12]);
+        a.m[13] = __builtin_fma(wxy, yy, a.m[13]);
+        a.m[14] = __builtin_fma(wyy, yy, a.m[14]);
+        if constexpr (HAS_B) {
+          a.b[3] = __builtin_fma(fd, wxx, a.b[3]);
+          a.b[4] = __builtin_fma(fd, wxy, a.b[4]);
+          a.b[5] = __builtin_fma(fd, wyy, a.b[5]);
+        }
+      }
+    }
+  }
+}
+
+template <int ORDER>
+struct Fit64 {
+  double y[ORDER + 1], rho[ORDER + 1];
+  double g[ORDER + 1][n_basis<ORDER>()];  // A_o^-1 e0 of the orders solved
+};
+
+// Fits of orders 0..TOP (TOP <= ORDER) from FP64 moments: one LDL^T of the
+// order-TOP normal matrix (its leading blocks are the lower orders'), the
+// equilibrated pivots rho_o (0 unless every diagonal entry is positive) and,
+// for the orders `want` marks, g = A_o^-1 e0 and (with HAS_B) C0 = g . b.
+// Only L and z / D are kept, to hold down the registers of this rarely taken
+// path.
+template <int ORDER, int TOP, bool HAS_B>
+__device__ __forceinline__ void solve64(const Acc64<ORDER>& a, const bool* want, Fit64<ORDER>& out) {
+  constexpr int NB = n_basis<TOP>();
   constexpr int nb_tab[3] = {1, 3, 6};
   double L[NB][NB], D[NB];
   double rho = 1e300;
-  int o = 0;
+  bool diag = true;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const double ajj = m[aidx(j, j)];
+    const double ajj = a.m[aidx(j, j)];
+    diag = diag && ajj > 0.0;
     double d = ajj;
 #pragma unroll
     for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k] * D[k];
     D[j] = d;
     const double req = ajj > 0.0 ? d / ajj : 0.0;
     rho = req < rho ? req : rho;
-    const double id = d > 0.0 ? 1.0 / d : 0.0;
+    if (j + 1 < NB) {
+      const double id = d > 0.0 ? 1.0 / d : 0.0;
 #pragma unroll
-    for (int i = j + 1; i < NB; ++i) {
-      double t = m[aidx(i, j)];
+      for (int i = j + 1; i < NB; ++i) {
+        double t = a.m[aidx(i, j)];
 #pragma unroll
-      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k] * D[k];
-      L[i][j] = t * id;
+        for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k] * D[k];
+        L[i][j] = t * id;
+      }
     }
-    if (j == nb_tab[o] - 1) {
-      rho_o[o] = rho > 0.0 ? rho : 0.0;
-      ++o;
-    }
+#pragma unroll
+    for (int o = 0; o <= TOP; ++o)
+      if (j == nb_tab[o] - 1) out.rho[o] = (diag && rho > 0.0) ? rho : 0.0;
   }
-}
-
-// FP64 refinement of an ill-conditioned order-2 solve.  The FP32 LDL^T of
-// the equilibrated matrix is recomputed here (cheaper than keeping it live),
-// then two steps of iterative refinement with the residual e0 - A g formed in
-// FP64 from the exact FP32 moments bring g = A^-1 e0 to FP64 solve accuracy
-// (the error left is that of the FP32 moments themselves).  C0 = g . b is
-// then summed in FP64.  The variance is recomputed by the caller from g.
-__device__ __forceinline__ void refine_order2(const float* m, const float* b, float* g, float& y) {
-  constexpr int NB = 6;
-  float s[NB], L[NB][NB], D[NB], iD[NB];
+  // forward substitution of e0 (shared by every order), then z_i / D_i
+  double z[NB];
+  z[0] = 1.0;
 #pragma unroll
-  for (int i = 0; i < NB; ++i) s[i] = __builtin_amdgcn_rsqf(m[aidx(i, i)]);
+  for (int i = 1; i < NB; ++i) {
+    double t = 0.0;
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    float d = s[j] * s[j] * m[aidx(j, j)];
-#pragma unroll
-    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k] * D[k];
-    D[j] = d;
-    iD[j] = d > 0.f ? __builtin_amdgcn_rcpf(d) : 0.f;
-#pragma unroll
-    for (int i = j + 1; i < NB; ++i) {
-      float t = s[i] * s[j] * m[aidx(i, j)];
-#pragma unroll
-      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k] * D[k];
-      L[i][j] = t * iD[j];
-    }
+    for (int k = 0; k < i; ++k) t -= L[i][k] * z[k];
+    z[i] = t;
   }
 #pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    float t[NB];
+  for (int i = 0; i < NB; ++i) z[i] = D[i] > 0.0 ? z[i] / D[i] : 0.0;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      double r = (i == 0) ? 1.0 : 0.0;
+  for (int o = 0; o <= ORDER; ++o) {
+    out.y[o] = 0.0;
 #pragma unroll
-      for (int j = 0; j < NB; ++j) r -= (double)m[aidx(i, j)] * (double)g[j];
-      t[i] = (float)r * s[i];
-    }
-    // solve A~ x = t with the FP32 factors, then g += S x
-#pragma unroll
-    for (int i = 1; i < NB; ++i)
-#pragma unroll
-      for (int k = 0; k < i; ++k) t[i] -= L[i][k] * t[k];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) t[i] *= iD[i];
-#pragma unroll
-    for (int i = NB - 1; i >= 0; --i)
-#pragma unroll
-      for (int k = i + 1; k < NB; ++k) t[i] -= L[k][i] * t[k];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) g[i] += s[i] * t[i];
+    for (int i = 0; i < n_basis<ORDER>(); ++i) out.g[o][i] = 0.0;
   }
-  double acc = 0.0;
 #pragma unroll
-  for (int i = 0; i < NB; ++i) acc += (double)g[i] * (double)b[i];
-  y = (float)acc;
+  for (int o = 0; o <= TOP; ++o) {
+    if (!want[o]) continue;
+    const int no = nb_tab[o];
+    double y = 0.0;
+#pragma unroll
+    for (int i = NB - 1; i >= 0; --i) {
+      if (i < no) {
+        double t = z[i];
+#pragma unroll
+        for (int k = i + 1; k < NB; ++k)
+          if (k < no) t -= L[k][i] * out.g[o][k];
+        out.g[o][i] = t;
+        if constexpr (HAS_B) y = __builtin_fma(t, a.b[i], y);
+      }
+    }
+    out.y[o] = y;
+  }
+#pragma unroll
+  for (int o = TOP + 1; o <= ORDER; ++o) out.rho[o] = 0.0;
 }
 
 // ICI running state of one order (reading: Goldenshluger-Nemirovski rule).
 struct IciState {
   float lo, hi, y, sd;
+  float risk;  // chosen fit: rounding bound of C0 over max(|C0|, value floor)
+               // (+inf for fits whose FP32 value carries no bound)
   int chosen;
   bool stopped, any;
 };
@@ -394,12 +499,14 @@ __device__ __forceinline__ void ici_init(IciState& st) {
   st.hi = __builtin_inff();
   st.y = __builtin_nanf("");
   st.sd = __builtin_nanf("");
+  st.risk = 0.f;
   st.chosen = -1;
   st.stopped = false;
   st.any = false;
 }
 
-__device__ __forceinline__ void ici_step(IciState& st, bool ok, float y, float v, float gamma, int m) {
+__device__ __forceinline__ void ici_step(IciState& st, bool ok, float y, float v, float gamma, int m,
+                                         float risk) {
   if (!ok) return;
   st.any = true;
   if (st.stopped) return;
@@ -410,6 +517,7 @@ __device__ __forceinline__ void ici_step(IciState& st, bool ok, float y, float v
     st.chosen = m;
     st.y = y;
     st.sd = sd;
+    st.risk = risk;
   } else {
     st.stopped = true;
   }
@@ -427,20 +535,24 @@ __device__ __forceinline__ float2 decode_dn(const SensorK& S, float y) {
   return make_float2(yb * S.inv_ge, __builtin_amdgcn_rcpf(var));
 }
 
-// The same with the pixel's calibration frames c = (b_i, 1 / (g n a_i),
-// Var[r_i], saturation_i) (Sec. 6 eq. Efsi and varianceestiamte with a_i and
-// the bias and saturation frames).
+// The same with the pixel's calibration frames c = (b_i, a_i, Var[r_i],
+// saturation_i) (Sec. 6 eq. Efsi and varianceestiamte with a_i and the bias
+// and saturation frames): scale 1 / (g n a_i).
 __device__ __forceinline__ float2 decode_dn_cal(const SensorK& S, float y, float4 c) {
   if (!(y < c.w)) return make_float2(0.f, 0.f);
   const float yb = y - c.x;
-  const float var = __builtin_fmaf(S.gain, fmaxf(yb, 0.f), c.z) * (c.y * c.y);
-  return make_float2(yb * c.y, __builtin_amdgcn_rcpf(var));
+  const float sc = S.inv_ge * __builtin_amdgcn_rcpf(c.y);
+  const float var = __builtin_fmaf(S.gain, fmaxf(yb, 0.f), c.z) * (sc * sc);
+  return make_float2(yb * sc, __builtin_amdgcn_rcpf(var));
 }
 
+// FP16 planes hold v = (y - 2^(bits-1)) 2^-bits (+Inf where masked): raw
+// values of up to 12 bits come back exactly, y = v 2^bits + 2^(bits-1), so
+// the decode then equals decode_dn's.  Masking was decided on the raw value.
 __device__ __forceinline__ float2 decode_f16(const SensorK& S, __half h) {
   const float v = __half2float(h);
   if (__builtin_isinf(v)) return make_float2(0.f, 0.f);
-  const float yb = v * S.norm_decode;  // exact: power-of-two scale
+  const float yb = __builtin_fmaf(v, S.norm_decode, S.norm_offset) - S.black;
   const float var = __builtin_fmaf(S.gain, fmaxf(yb, 0.f), S.read_var) * (S.inv_ge * S.inv_ge);
   return make_float2(yb * S.inv_ge, __builtin_amdgcn_rcpf(var));
 }
@@ -459,13 +571,14 @@ __device__ __forceinline__ float2 load_sample(const SensorK& S, int x, int y) {
   } else {
     const __half h = reinterpret_cast<const __half*>(row)[x];
     if (S.calib) {
-      // FP16 planes hold (y - b_i) 2^-bits; the frames give the pixel's scale and readout variance
+      // as decode_f16, with the pixel's bias, scale and readout variance
       const float v = __half2float(h);
       if (__builtin_isinf(v)) return make_float2(0.f, 0.f);
       const float4 c = S.calib[(int64_t)y * S.width + x];
-      const float yb = v * S.norm_decode;
-      const float var = __builtin_fmaf(S.gain, fmaxf(yb, 0.f), c.z) * (c.y * c.y);
-      return make_float2(yb * c.y, __builtin_amdgcn_rcpf(var));
+      const float yb = __builtin_fmaf(v, S.norm_decode, S.norm_offset) - c.x;
+      const float sc = S.inv_ge * __builtin_amdgcn_rcpf(c.y);
+      const float var = __builtin_fmaf(S.gain, fmaxf(yb, 0.f), c.z) * (sc * sc);
+      return make_float2(yb * sc, __builtin_amdgcn_rcpf(var));
     }
     return decode_f16(S, h);
   }
@@ -645,6 +758,205 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 refit from the raw frame.  Outputs whose FP32 value could be off by
+// more than the target are recomputed as the model defines them, in FP64
+// throughout: each raw sample is re-read from the frame and decoded (Sec. 6
+// eq. Efsi, Sec. 6.1 eq. varianceestiamte, with the pixel's calibration
+// frames), placed by the FP64 sensor map (Sec. 4.2), weighted by the FP64
+// window of the chosen radius, and the normal equations are accumulated and
+// solved in FP64.  Where C0 is a small difference of large terms, even the
+// FP32 rounding of a sample's position or weight moves it by more than the
+// target, so the refit keeps nothing of the FP32 pass but its decision.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool decode64(const SensorK& S, int x, int y, double& f, double& iv) {
+  const char* row = static_cast<const char*>(S.raw) + (int64_t)y * S.raw_pitch;
+  const double dn = S.raw_f32 ? (double)reinterpret_cast<const float*>(row)[x]
+                              : (double)reinterpret_cast<const uint16_t*>(row)[x];
+  double b = S.black64, a = 1.0, rv = S.read_var64, sat = S.sat64;
+  if (S.calib) {
+    const float4 c = S.calib[(int64_t)y * S.width + x];
+    b = c.x;
+    a = c.y;
+    rv = c.z;
+    sat = c.w;
+  }
+  if (!(dn < sat)) return false;
+  const double ga = S.ge64 * a;
+  f = (dn - b) / ga;
+  iv = (ga * ga) / (S.gain64 * ga * fmax(f, 0.0) + rv);
+  return true;
+}
+
+// One FP64 sample (unscaled offset x, y; radiance f; weight w) into the
+// normal equations of every order up to ORDER.
+template <int ORDER>
+__device__ __forceinline__ void acc64_d(Acc64<ORDER>& a, double x, double y, double f, double w) {
+  a.m[0] += w;
+  a.b[0] = __builtin_fma(w, f, a.b[0]);
+  if constexpr (ORDER >= 1) {
+    const double wx = w * x, wy = w * y;
+    const double wxx = wx * x, wxy = wx * y, wyy = wy * y;
+    a.m[1] += wx;
+    a.m[2] += wy;
+    a.m[3] += wxx;
+    a.m[4] += wxy;
+    a.m[5] += wyy;
+    a.b[1] = __builtin_fma(f, wx, a.b[1]);
+    a.b[2] = __builtin_fma(f, wy, a.b[2]);
+    if constexpr (ORDER >= 2) {
+      const double xx = x * x, yy = y * y;
+      a.m[6] = __builtin_fma(wxx, x, a.m[6]);
+      a.m[7] = __builtin_fma(wxx, y, a.m[7]);
+      a.m[8] = __builtin_fma(wyy, x, a.m[8]);
+      a.m[9] = __builtin_fma(wyy, y, a.m[9]);
+      a.m[10] = __builtin_fma(wxx, xx, a.m[10]);
+      a.m[11] = __builtin_fma(wxy, xx, a.m[11]);
+      a.m[12] = __builtin_fma(wxx, yy, a.m[12]);
+      a.m[13] = __builtin_fma(wxy, yy, a.m[13]);
+      a.m[14] = __builtin_fma(wyy, yy, a.m[14]);
+      a.b[3] = __builtin_fma(f, wxx, a.b[3]);
+      a.b[4] = __builtin_fma(f, wxy, a.b[4]);
+      a.b[5] = __builtin_fma(f, wyy, a.b[5]);
+    }
+  }
+}
+
+// C0 of output pixel (u, v), channel c, at radius index m and order o (<=
+// ORDER), in FP64 from the raw frame; steered windows read the pixel's
+// steering matrix.  Every sensor's box covers the window: the disc of radius
+// r' (the ellipse d^T C d < r'^2, whose half-width along a sensor axis with
+// inverse-map row a is r' sqrt(a^T C^-1 a)).  One lane per output.
+template <int ORDER, bool STEER>
+__device__ double refit_one(const LaunchK& K, int u, int v, int c, int o, int m) {
+  const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
+  const double Yj = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
+  const int cls = (c == 1) ? 1 : 0;
+  const double r = K.sc[m].radius[cls];
+  const double r2 = r * r, ih = 1.0 / K.sc[m].h[cls];
+  const double ee = exp(-r2 * ih);
+  double cxx = 1.0, cxy = 0.0, cyy = 1.0, ixx = 1.0, ixy = 0.0, iyy = 1.0;  // C and C^-1
+  if constexpr (STEER) {
+    const float4 q = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(K.steer) +
+                                                     (int64_t)v * K.steer_pitch)[u];
+    cxx = q.x;
+    cxy = q.y;
+    cyy = q.z;
+    const double id = 1.0 / (cxx * cyy - cxy * cxy);
+    ixx = cyy * id;
+    iyy = cxx * id;
+    ixy = -cxy * id;
+  }
+  Acc64<ORDER> a;
+  acc64_zero(a);
+  for (int s = 0; s < K.n_sensors; ++s) {
+    const SensorK& S = K.s[s];
+    const double px = S.inv[0] * Xj + S.inv[1] * Yj + S.inv[2];
+    const double py = S.inv[3] * Xj + S.inv[4] * Yj + S.inv[5];
+    const double ax = S.inv[0], ay = S.inv[1], bx = S.inv[3], by = S.inv[4];
+    const double wx = r * sqrt(ax * ax * ixx + 2.0 * ax * ay * ixy + ay * ay * iyy) * (1.0 + 1e-12);
+    const double wy = r * sqrt(bx * bx * ixx + 2.0 * bx * by * ixy + by * by * iyy) * (1.0 + 1e-12);
+    const int nx = max(1, (int)ceil(wx - 1e-9)), ny = max(1, (int)ceil(wy - 1e-9));
+    for (int q = 0; q < S.sub_n[c]; ++q) {
+      const int ox = S.sub_ox[c][q], oy = S.sub_oy[c][q];
+      const int xb = ox + 2 * (int)ceil((px - wx - ox) * 0.5);
+      const int yb = oy + 2 * (int)ceil((py - wy - oy) * 0.5);
+      for (int j = 0; j < ny; ++j) {
+        const int y = yb + 2 * j;
+        if (y < 0 || y >= S.height) continue;
+        for (int i = 0; i < nx; ++i) {
+          const int x = xb + 2 * i;
+          if (x < 0 || x >= S.width) continue;
+          const double dX = S.fwd[0] * x + S.fwd[1] * y + S.fwd[2] - Xj;
+          const double dY = S.fwd[3] * x + S.fwd[4] * y + S.fwd[5] - Yj;
+          const double d2 = STEER ? cxx * dX * dX + 2.0 * cxy * dX * dY + cyy * dY * dY : dX * dX + dY * dY;
+          if (!(d2 < r2)) continue;
+          double f, iv;
+          if (decode64(S, x, y, f, iv)) acc64_d<ORDER>(a, dX, dY, f, (exp(-d2 * ih) - ee) * iv);
+        }
+      }
+    }
+  }
+  bool want[ORDER + 1];
+#pragma unroll
+  for (int k = 0; k <= ORDER; ++k) want[k] = k == o;
+  Fit64<ORDER> fit;
+  solve64<ORDER, ORDER, true>(a, want, fit);
+  double y = 0.0;
+#pragma unroll
+  for (int k = 0; k <= ORDER; ++k)
+    if (k == o) y = fit.y[k];
+  return y;
+}
+
+// The refit of one tile: its marked outputs are gathered in LDS, then each
+// lane of the workgroup takes one.
+template <int ORDER, bool STEER>
+__device__ __forceinline__ void refit_tile(const LaunchK& K, int tile, uint16_t* list, int* count) {
+  const int u0 = (tile % K.tiles_x) * K.tile_w, v0 = (tile / K.tiles_x) * K.tile_h;
+  const int n_out = K.tile_w * K.tile_h * 3;
+  if (threadIdx.x == 0) *count = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_out; t += blockDim.x) {
+    const int p = t / 3, c = t - 3 * p;
+    const int u = u0 + p % K.tile_w, v = v0 + p / K.tile_w;
+    if (u < K.out_w && v < K.out_h && (K.refit_map[(int64_t)v * K.refit_pitch + 3 * u + c] & 0x80))
+      list[atomicAdd(count, 1)] = (uint16_t)t;
+  }
+  __syncthreads();
+  const int n = *count;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int t = list[i];
+    const int p = t / 3, c = t - 3 * p;
+    const int u = u0 + p % K.tile_w, v = v0 + p / K.tile_w;
+    const int code = K.refit_map[(int64_t)v * K.refit_pitch + 3 * u + c];
+    const double y = refit_one<ORDER, STEER>(K, u, v, c, (code >> 4) & 3, code & 7);
+    float* orow = reinterpret_cast<float*>(reinterpret_cast<char*>(K.rgb) + (int64_t)v * K.rgb_pitch);
+    orow[3 * u + c] = (float)y;
+  }
+  __syncthreads();
+}
+
+constexpr int kRefitBlock = 64;
+
+template <int ORDER, bool STEER>
+__global__ void __launch_bounds__(kRefitBlock) refit_kernel(const LaunchK K) {
+  __shared__ uint16_t list[768];
+  __shared__ int count;
+  refit_tile<ORDER, STEER>(K, blockIdx.x, list, &count);
+}
+
+// Batch form: workgroups take tiles t = blockIdx.x, blockIdx.x + gridDim.x, ...
+template <int ORDER>
+__device__ __forceinline__ void refit_batch_tile(const LaunchK& K, int local, uint16_t* list, int* count) {
+  refit_tile<ORDER, false>(K, local, list, count);
+}
+
+__global__ void __launch_bounds__(kRefitBlock) refit_batch_kernel(const BatchHeader* __restrict__ hdr,
+                                                                  const LaunchK* __restrict__ frames,
+                                                                  const int64_t* __restrict__ first_tile) {
+  __shared__ uint16_t list[768];
+  __shared__ int count;
+  const int n_frames = hdr->n_frames;
+  const int64_t total = hdr->total_tiles;
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = n_frames - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (first_tile[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int f = __builtin_amdgcn_readfirstlane(lo);
+    const LaunchK& K = frames[f];
+    if (!K.refit_map) continue;
+    const int local = (int)(t - first_tile[f]);
+    switch (K.order) {
+      case 0: refit_batch_tile<0>(K, local, list, &count); break;
+      case 1: refit_batch_tile<1>(K, local, list, &count); break;
+      default: refit_batch_tile<2>(K, local, list, &count); break;
+    }
+  }
+}
+
 // Pre-computed window weights: one tabulated sample of a stencil.  The entry
 // holds K * monomial for every Hankel moment, so A, b and B take one FMA per
 // moment each (w = K iv, w f and K w are formed once per sample).  Returns
@@ -652,6 +964,7 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
 template <int ORDER, bool ICI>
 __device__ __forceinline__ bool acc_entry(Acc<ORDER, ICI>& a, const ConstEntry& e, float f, float iv) {
   const float wf = f * iv;
+  a.f2 = __builtin_fmaf(e.a[0] * wf, f, a.f2);
 #pragma unroll
   for (int k = 0; k < n_mom<ORDER>(); ++k) a.m[k] = __builtin_fmaf(e.a[k], iv, a.m[k]);
 #pragma unroll
@@ -699,9 +1012,11 @@ __device__ __forceinline__ void walk_stencil(const LaunchK& K, const float2* lds
   }
 }
 
+// cnt64 / cnt_nan count this lane's outputs marked for the FP64 refit and
+// those with no valid fit.
 template <int ORDER, bool ICI, bool STEER, bool STENCIL = false>
 __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, const Region* regs,
-                                          int u, int v, bool active) {
+                                          int u, int v, bool active, int& cnt64, int& cnt_nan) {
   const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
   const double Yj = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
   SteerC sc = {1.f, 1.f, 0.f};  // lanes outside the grid keep the isotropic window (inside the box)
@@ -766,157 +1081,146 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
       // for fallback) are no longer solved.
       const bool lower = __builtin_amdgcn_ballot_w64(!st[ORDER].any) != 0;
       Fits<float, ORDER> fr;
-      solve_fits<float, ORDER, ICI>(a.m, a.b, a.B, K.tau_inv, lower, fr);
-      if constexpr (ORDER == 2) {
-        // ill-conditioned order-2 solves: FP64 iterative refinement
-        if (K.use_fp64 && fr.ok[2] && fr.rho[2] < K.tau_fp64) refine_order2(a.m, a.b, fr.g[2], fr.y[2]);
-      }
+      solve_fits<float, ORDER, ICI, true>(a.m, a.b, a.B, K.tau_inv, lower, fr, a.f2);
+      // The top order's rounding risk, formed here: the empty asm keeps the
+      // compiler from sinking the bound's arithmetic (and with it the factors
+      // it reads) past the FP64 pass below.
+      float risk_top = fr.s[ORDER] / fmaxf(fabsf(fr.y[ORDER]), K.value_floor);
+      asm volatile("" : "+v"(risk_top));
+      bool x64[ORDER + 1];
+#pragma unroll
+      for (int o = 0; o <= ORDER; ++o) x64[o] = false;
       if constexpr (ORDER >= 1) {
         // Validity where the FP32 pivot cannot certify it (rho < the bound
         // kPivotCertifiesN) needs the support size N and, if N >= n_o, the
         // pivots of the normal matrix accumulated in FP64.  A counted support
-        // smaller than n_o decides the fit at once.
+        // smaller than n_o decides the fit at once.  Fits decided on FP64
+        // pivots, and valid fits with rho < tau_fp64, take their value and
+        // variance from the FP64 moments too.
         constexpr int nb_tab[3] = {1, 3, 6};
-        bool small1 = false, small2 = false, need_var = false;
+        bool small[ORDER + 1], dbl[ORDER + 1];
+        small[0] = dbl[0] = false;
+        bool any_dbl = false;
 #pragma unroll
         for (int o = 1; o <= ORDER; ++o) {
-          bool sm = (o == ORDER || lower) && fr.rho[o] < kPivotCertifiesN;
+          const bool used = o == ORDER || lower;
+          bool sm = used && fr.rho[o] < kPivotCertifiesN;
           if (sm && n_first >= 0 && n_first < nb_tab[o]) {
             fr.ok[o] = false;
             sm = false;
           }
-          if (o == 1) small1 = sm;
-          else small2 = sm;
-          need_var = need_var || (ICI && fr.ok[o] && fr.rho[o] < K.tau_fp64);
+          small[o] = sm;
+          dbl[o] = sm || (K.use_fp64 && used && fr.ok[o] && fr.rho[o] < K.tau_fp64);
+          any_dbl = any_dbl || dbl[o];
         }
-        // Second pass over the samples, taken by the whole wave when any lane
-        // needs it: FP64 moments (of order 2 only where an order-2 fit needs
-        // them) and, for ill-conditioned fits, the variance from positive terms.
-        const bool pass64 = __builtin_amdgcn_ballot_w64(small1 || small2) != 0;
-        const bool pass64_2 = ORDER >= 2 && __builtin_amdgcn_ballot_w64(small2) != 0;
-        if (pass64 || __builtin_amdgcn_ballot_w64(need_var) != 0) {
+        // A second pass over the samples, taken by the whole wave when any
+        // lane needs it, accumulates the normal matrix in FP64 (the order-2
+        // sums only where an order-2 fit needs them) and counts the support.
+        // The fits it redoes then take C0 = sum_k (g . phi_k) w_k f_k and
+        // var C0 = sum_k (g . phi_k)^2 K_k w_k (positive terms: the moment
+        // form g^T B g cancels badly at small pivots) from a third pass, with
+        // g from the FP64 solve.
+        if (__builtin_amdgcn_ballot_w64(any_dbl) != 0) {
+          const bool hi = ORDER >= 2 && __builtin_amdgcn_ballot_w64(dbl[ORDER]) != 0;
+          Acc64<ORDER> a64;
+          acc64_zero(a64);
           int n = 0;
-          double m64[n_mom<ORDER>()];
-#pragma unroll
-          for (int k = 0; k < n_mom<ORDER>(); ++k) m64[k] = 0.0;
-          float vs[ORDER + 1];
-#pragma unroll
-          for (int o = 0; o <= ORDER; ++o) vs[o] = 0.f;
           auto second = [&](float dx, float dy, float f, float iv) {
             (void)f;
-            const float x2 = dx * dx, y2 = dy * dy;
-            const float r2 = window_r2<STEER>(dx, dy, x2, y2, sc);
+            const float r2 = window_r2<STEER>(dx, dy, dx * dx, dy * dy, sc);
             if (r2 < reach2) {
-              const float kw = fmaxf(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f);
-              const float w = kw * iv;
-              if (pass64) {
-                n += (w > 0.f) ? 1 : 0;
-                const double wd = w, x = dx, y = dy;
-                const double xx = x * x, xy = x * y, yy = y * y;
-                m64[0] += wd;
-                m64[1] += wd * x;
-                m64[2] += wd * y;
-                m64[3] += wd * xx;
-                m64[4] += wd * xy;
-                m64[5] += wd * yy;
-                if constexpr (ORDER >= 2) {
-                  if (pass64_2) {
-                    m64[6] += wd * xx * x;
-                    m64[7] += wd * xx * y;
-                    m64[8] += wd * xy * y;
-                    m64[9] += wd * yy * y;
-                    m64[10] += wd * xx * xx;
-                    m64[11] += wd * xx * xy;
-                    m64[12] += wd * xx * yy;
-                    m64[13] += wd * xy * yy;
-                    m64[14] += wd * yy * yy;
-                  }
-                }
-              }
-              if constexpr (ICI) {
-                const float w2 = w * kw;
-                float phi[6] = {1.f, dx, dy, x2, dx * dy, y2};
-#pragma unroll
-                for (int o = 1; o <= ORDER; ++o) {
-                  float t = fr.g[o][0];
-#pragma unroll
-                  for (int i = 1; i < nb_tab[o]; ++i) t = __builtin_fmaf(fr.g[o][i], phi[i], t);
-                  vs[o] = __builtin_fmaf(t * t, w2, vs[o]);
-                }
-              }
+              const float w = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f, 1.f) * iv;
+              n += (w > 0.f) ? 1 : 0;
+              acc64_sample<ORDER, false>(a64, dx, dy, 0.f, w, hi);
             }
           };
-          if constexpr (STENCIL) {
-            // the same sums over tabulated samples: K * monomial comes from the
-            // entry, and (g . phi)^2 K w = (g . (K phi))^2 iv
-            auto second_e = [&](const ConstEntry& e, float f, float iv) {
-              (void)f;
-              if (pass64) {
-                n += (iv > 0.f) ? 1 : 0;
-                const double ivd = iv;
+          walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, second);
+          Fit64<ORDER> r64;
+          if (hi) solve64<ORDER, ORDER, false>(a64, dbl, r64);
+          else solve64<ORDER, 1, false>(a64, dbl, r64);  // only order-1 fits to redo
+          bool redo[ORDER + 1];
+          bool any_redo = false;
+          redo[0] = false;
 #pragma unroll
-                for (int k = 0; k < 6; ++k) m64[k] += (double)e.a[k] * ivd;
-                if constexpr (ORDER >= 2) {
-                  if (pass64_2) {
+          for (int o = 1; o <= ORDER; ++o) {
+            if (small[o]) {
+              fr.rho[o] = (float)r64.rho[o];
+              fr.ok[o] = r64.rho[o] >= (double)K.tau_inv && n >= nb_tab[o];
+            }
+            redo[o] = dbl[o] && fr.ok[o];
+            any_redo = any_redo || redo[o];
+          }
+          if (__builtin_amdgcn_ballot_w64(any_redo) != 0) {
+            double ys[ORDER + 1];
+            float vs[ORDER + 1];
 #pragma unroll
-                    for (int k = 6; k < 15; ++k) m64[k] += (double)e.a[k] * ivd;
-                  }
-                }
-              }
-              if constexpr (ICI) {
+            for (int o = 0; o <= ORDER; ++o) {
+              ys[o] = 0.0;
+              vs[o] = 0.f;
+            }
+            auto third = [&](float dx, float dy, float f, float iv) {
+              const float x2 = dx * dx, y2 = dy * dy;
+              const float r2 = window_r2<STEER>(dx, dy, x2, y2, sc);
+              if (r2 < reach2) {
+                const float kw = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f, 1.f);
+                const float w = kw * iv;
+                const double x = dx, y = dy, wf = (double)w * (double)f;
+                const double phi[6] = {1.0, x, y, x * x, x * y, y * y};
 #pragma unroll
                 for (int o = 1; o <= ORDER; ++o) {
-                  float t = fr.g[o][0] * e.a[0];
+                  double t = r64.g[o][0];
 #pragma unroll
-                  for (int i = 1; i < nb_tab[o]; ++i) t = __builtin_fmaf(fr.g[o][i], e.a[i], t);
-                  vs[o] = __builtin_fmaf(t * t, iv, vs[o]);
+                  for (int i = 1; i < nb_tab[o]; ++i) t = __builtin_fma(r64.g[o][i], phi[i], t);
+                  ys[o] = __builtin_fma(t, wf, ys[o]);
+                  if constexpr (ICI) {
+                    const float tf = (float)t;
+                    vs[o] = __builtin_fmaf(tf * tf, w * kw, vs[o]);
+                  }
                 }
               }
             };
-            walk_stencil(K, lds, regs, u, v, c, par, m, second_e);
-          } else {
-            walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, second);
-          }
-          if (pass64) {
-            double r64[ORDER + 1];
-            if constexpr (ORDER >= 2) {
-              if (pass64_2) pivots_fp64<2>(m64, r64);
-              else pivots_fp64<1>(m64, r64);  // only order-1 fits to decide
-            } else {
-              pivots_fp64<ORDER>(m64, r64);
-            }
+            walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, third);
 #pragma unroll
             for (int o = 1; o <= ORDER; ++o) {
-              if ((o == 1) ? small1 : small2) {
-                bool diag = true;
-#pragma unroll
-                for (int i = 0; i < nb_tab[o]; ++i) diag = diag && m64[aidx(i, i)] > 0.0;
-                fr.rho[o] = diag ? (float)r64[o] : 0.f;
-                fr.ok[o] = diag && r64[o] >= (double)K.tau_inv && n >= nb_tab[o];
+              if (redo[o]) {
+                fr.y[o] = (float)ys[o];
+                if constexpr (ICI) fr.v[o] = vs[o];
+                x64[o] = true;
               }
             }
-          }
-          if constexpr (ICI) {
-#pragma unroll
-            for (int o = 1; o <= ORDER; ++o)
-              if (fr.rho[o] < K.tau_fp64) fr.v[o] = vs[o];
           }
         }
       }
 #pragma unroll
       for (int o = 0; o <= ORDER; ++o)
-        if (o == ORDER || lower) ici_step(st[o], fr.ok[o], fr.y[o], fr.v[o], K.gamma, m);
+        if (o == ORDER || lower)
+          ici_step(st[o], fr.ok[o], fr.y[o], fr.v[o], K.gamma, m,
+                   (o == ORDER && !x64[o]) ? risk_top : __builtin_inff());
     }
 
+    // the chosen order (highest with a valid fit) and its ICI result
     float val = __builtin_nanf(""), sdc = __builtin_nanf("");
     uint8_t cd = 0xFF;
+    int mc = -1;
+    float risk = 0.f;
 #pragma unroll
     for (int o = ORDER; o >= 0; --o) {
       if (cd == 0xFF && st[o].any) {
         val = st[o].y;
         sdc = st[o].sd;
         cd = (uint8_t)((o << 4) | st[o].chosen);
+        mc = st[o].chosen;
+        risk = st[o].risk;
       }
+    }
+    // Outputs whose FP32 rounding bound exceeds the target are marked for the
+    // FP64 refit launch (refit_kernel), which recomputes them at the chosen
+    // radius and order from the raw frame.
+    const bool refit = active && mc >= 0 && risk > K.risk_max;
+    if (active) {
+      if (K.refit_map) K.refit_map[(int64_t)v * K.refit_pitch + 3 * u + c] = refit ? (uint8_t)(0x80 | cd) : 0;
+      cnt64 += refit ? 1 : 0;
+      cnt_nan += cd == 0xFF ? 1 : 0;
     }
     // written as soon as the channel is done: nothing of it stays live
     // through the next channel's walks
@@ -932,21 +1236,38 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
   }
 }
 
+// Per-workgroup LDS beside the staged samples.
+struct TileShared {
+  Region regs[kMaxSensors];
+  uint32_t stat[2];  // the tile's FP64-valued and no-data outputs
+};
+
 template <int ORDER, bool ICI, int SRC, bool STEER = false, bool STENCIL = false>
-__device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2* lds, Region* regs) {
+__device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2* lds, TileShared& sh) {
   const int tx = tile % K.tiles_x;
   const int ty = tile / K.tiles_x;
   const int u0 = tx * K.tile_w, v0 = ty * K.tile_h;
   const int tid = threadIdx.x;
   const int nthreads = K.tile_w * K.tile_h;
-  stage_tile<SRC, STENCIL>(K, u0, v0, lds, regs, tid, nthreads);
+  if (tid < 2) sh.stat[tid] = 0u;
+  stage_tile<SRC, STENCIL>(K, u0, v0, lds, sh.regs, tid, nthreads);
   __syncthreads();
   int du, dv;
   lane_pixel(tid, K.tile_w, K.tile_h, &du, &dv);
   const int u = u0 + du, v = v0 + dv;
   const bool active = (u < K.out_w) && (v < K.out_h);
   // inactive lanes of a ragged tile compute at their nominal pixel (staged)
-  fit_pixel<ORDER, ICI, STEER, STENCIL>(K, lds, regs, u, v, active);
+  int cnt64 = 0, cnt_nan = 0;
+  fit_pixel<ORDER, ICI, STEER, STENCIL>(K, lds, sh.regs, u, v, active, cnt64, cnt_nan);
+  if (K.tile_stats) {
+    if (cnt64) atomicAdd(&sh.stat[0], (uint32_t)cnt64);
+    if (cnt_nan) atomicAdd(&sh.stat[1], (uint32_t)cnt_nan);
+    __syncthreads();
+    if (tid == 0) {
+      K.tile_stats[2 * tile] = sh.stat[0];
+      K.tile_stats[2 * tile + 1] = sh.stat[1];
+    }
+  }
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup i runs on
@@ -960,11 +1281,12 @@ __device__ __forceinline__ int xcd_tile(int i, int n) {
   return x * q + (x < r ? x : r) + j;
 }
 
+// Compiled for at least 3 waves per SIMD (<= 168 VGPRs).
 template <int ORDER, bool ICI, int SRC>
-__global__ void __launch_bounds__(256) fit_kernel(const LaunchK K) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) fit_kernel(const LaunchK K) {
   extern __shared__ float2 lds[];
-  __shared__ Region regs[kMaxSensors];
-  process_tile<ORDER, ICI, SRC>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
+  __shared__ TileShared sh;
+  process_tile<ORDER, ICI, SRC>(K, xcd_tile(blockIdx.x, gridDim.x), lds, sh);
 }
 
 // Same kernel compiled for 4 waves per SIMD (<= 128 VGPRs: some values spill
@@ -974,8 +1296,8 @@ template <int ORDER, bool ICI, int SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 fit_kernel_occ4(const LaunchK K) {
   extern __shared__ float2 lds[];
-  __shared__ Region regs[kMaxSensors];
-  process_tile<ORDER, ICI, SRC>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
+  __shared__ TileShared sh;
+  process_tile<ORDER, ICI, SRC>(K, xcd_tile(blockIdx.x, gridDim.x), lds, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -987,8 +1309,8 @@ template <int ORDER, bool ICI, int SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 fit_kernel_steer(const LaunchK K) {
   extern __shared__ float2 lds[];
-  __shared__ Region regs[kMaxSensors];
-  process_tile<ORDER, ICI, SRC, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
+  __shared__ TileShared sh;
+  process_tile<ORDER, ICI, SRC, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, sh);
 }
 
 // Fit with pre-computed window weights (translation-only rigs, 256-lane
@@ -998,16 +1320,16 @@ template <int ORDER, bool ICI, int SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 fit_kernel_stencil(const LaunchK K) {
   extern __shared__ float2 lds[];
-  __shared__ Region regs[kMaxSensors];
-  process_tile<ORDER, ICI, SRC, false, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
+  __shared__ TileShared sh;
+  process_tile<ORDER, ICI, SRC, false, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, sh);
 }
 
 template <int ORDER, bool ICI, int SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 fit_kernel_stencil_occ4(const LaunchK K) {
   extern __shared__ float2 lds[];
-  __shared__ Region regs[kMaxSensors];
-  process_tile<ORDER, ICI, SRC, false, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, regs);
+  __shared__ TileShared sh;
+  process_tile<ORDER, ICI, SRC, false, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, sh);
 }
 
 // Full coefficient vector of one fit in FP64: LDL^T of A (as in solve_fits),
@@ -1196,7 +1518,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                                                        const int64_t* __restrict__ first_tile,
                                                        int* __restrict__ queue) {
   extern __shared__ float2 lds[];
-  __shared__ Region regs[kMaxSensors];
+  __shared__ TileShared sh;
   __shared__ int next_tile;
   const int n_frames = hdr->n_frames;
   const int64_t total_tiles = hdr->total_tiles;
@@ -1230,20 +1552,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     const LaunchK& K = frames[f];
     const int local = (int)(t - first_tile[f]);
     switch (K.order * 2 + (K.need_var ? 1 : 0)) {
-      case 0: process_tile<0, false, SRC>(K, local, lds, regs); break;
-      case 1: process_tile<0, true, SRC>(K, local, lds, regs); break;
-      case 2: process_tile<1, false, SRC>(K, local, lds, regs); break;
-      case 3: process_tile<1, true, SRC>(K, local, lds, regs); break;
-      case 4: process_tile<2, false, SRC>(K, local, lds, regs); break;
-      default: process_tile<2, true, SRC>(K, local, lds, regs); break;
+      case 0: process_tile<0, false, SRC>(K, local, lds, sh); break;
+      case 1: process_tile<0, true, SRC>(K, local, lds, sh); break;
+      case 2: process_tile<1, false, SRC>(K, local, lds, sh); break;
+      case 3: process_tile<1, true, SRC>(K, local, lds, sh); break;
+      case 4: process_tile<2, false, SRC>(K, local, lds, sh); break;
+      default: process_tile<2, true, SRC>(K, local, lds, sh); break;
     }
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Pre-pass: raw -> (radiance, inverse variance) FP32 plane, or raw ->
-// FP16 normalised radiance (y - b) 2^-bits, round-to-nearest-even, +Inf masked.
+// Pre-pass: raw -> (radiance, inverse variance) FP32 plane, or raw -> FP16
+// normalised value (y - 2^(bits-1)) 2^-bits, round-to-nearest-even (exact for
+// raw values of up to 12 bits), +Inf masked.
 // ---------------------------------------------------------------------------
 template <bool RAW_F32, bool TO_F16>
 __global__ void __launch_bounds__(256) prepass_kernel(const SensorK S, const void* raw, int64_t raw_pitch,
@@ -1258,7 +1581,7 @@ __global__ void __launch_bounds__(256) prepass_kernel(const SensorK S, const voi
   const bool cal = S.calib != nullptr;
   const float4 c = cal ? S.calib[(int64_t)y * S.width + x] : make_float4(S.black, S.inv_ge, S.read_var, S.sat);
   if constexpr (TO_F16) {
-    const __half h = (dn < c.w) ? __float2half_rn((dn - c.x) * norm_encode)
+    const __half h = (dn < c.w) ? __float2half_rn((dn - S.norm_offset) * norm_encode)
                                 : __ushort_as_half((unsigned short)0x7C00u);
     reinterpret_cast<__half*>(prow)[x] = h;
   } else {
@@ -1296,6 +1619,13 @@ int launch_fit_src(const LaunchK& K, hipStream_t st) {
     default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// Every sensor of a fit launch must name its raw plane (the FP64 refit reads it).
+bool raw_bound(const LaunchK& K) {
+  for (int s = 0; s < K.n_sensors; ++s)
+    if (!K.s[s].raw) return false;
+  return true;
 }
 
 }  // namespace
@@ -1356,7 +1686,7 @@ int launch_steer_src(const LaunchK& K, hipStream_t st) {
 
 extern "C" int lpa_k_fit_steered(const LaunchK* k, void* stream) {
   const LaunchK& K = *k;
-  if (!K.steer || K.tile_w * K.tile_h > 256 || (size_t)K.lds_floats2 * sizeof(float2) > (size_t)kMaxLdsBytes)
+  if (!raw_bound(K) || !K.steer || K.tile_w * K.tile_h > 256 || (size_t)K.lds_floats2 * sizeof(float2) > (size_t)kMaxLdsBytes)
     return -1;
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (K.order * 2 + (K.need_var ? 1 : 0)) {
@@ -1395,7 +1725,7 @@ int launch_stencil_src(const LaunchK& K, hipStream_t st) {
 extern "C" int lpa_k_fit_stencil(const LaunchK* k, void* stream) {
   const LaunchK& K = *k;
   // one parity class per wave needs 256-lane tiles
-  if (!K.stencil || K.tile_w * K.tile_h != 256 || (size_t)K.lds_floats2 * sizeof(float2) > (size_t)kMaxLdsBytes)
+  if (!raw_bound(K) || !K.stencil || K.tile_w * K.tile_h != 256 || (size_t)K.lds_floats2 * sizeof(float2) > (size_t)kMaxLdsBytes)
     return -1;
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (K.order * 2 + (K.need_var ? 1 : 0)) {
@@ -1411,7 +1741,7 @@ extern "C" int lpa_k_fit_stencil(const LaunchK* k, void* stream) {
 
 extern "C" int lpa_k_fit(const LaunchK* k, void* stream) {
   const LaunchK& K = *k;
-  if (K.tile_w * K.tile_h > 256 || (size_t)K.lds_floats2 * sizeof(float2) > (size_t)kMaxLdsBytes) return -1;
+  if (!raw_bound(K) || K.tile_w * K.tile_h > 256 || (size_t)K.lds_floats2 * sizeof(float2) > (size_t)kMaxLdsBytes) return -1;
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (K.order * 2 + (K.need_var ? 1 : 0)) {
     case 0: return launch_fit_src<0, false>(K, st);
@@ -1455,12 +1785,84 @@ extern "C" int lpa_k_fit_batch(const BatchHeader* d_hdr, const LaunchK* d_frames
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+extern "C" int lpa_k_refit(const LaunchK* k, void* stream) {
+  const LaunchK& K = *k;
+  if (!K.refit_map || !raw_bound(K) || K.tile_w * K.tile_h > 256) return -1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid(K.tiles_x * K.tiles_y), block(kRefitBlock);
+  const bool steer = K.steer != nullptr;
+  switch (K.order * 2 + (steer ? 1 : 0)) {
+    case 0: refit_kernel<0, false><<<grid, block, 0, st>>>(K); break;
+    case 1: refit_kernel<0, true><<<grid, block, 0, st>>>(K); break;
+    case 2: refit_kernel<1, false><<<grid, block, 0, st>>>(K); break;
+    case 3: refit_kernel<1, true><<<grid, block, 0, st>>>(K); break;
+    case 4: refit_kernel<2, false><<<grid, block, 0, st>>>(K); break;
+    case 5: refit_kernel<2, true><<<grid, block, 0, st>>>(K); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+extern "C" int lpa_k_refit_batch(const BatchHeader* hdr, const LaunchK* frames, const int64_t* first_tile,
+                                 int32_t grid, void* stream) {
+  refit_batch_kernel<<<grid, kRefitBlock, 0, static_cast<hipStream_t>(stream)>>>(hdr, frames, first_tile);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 namespace {
 __global__ void zero_i32_kernel(int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
 }
 }  // namespace
+
+namespace {
+// One workgroup of 256 threads sums n pairs of per-tile counts.
+__device__ void sum_pairs(const uint32_t* t, int64_t n, uint64_t* out) {
+  __shared__ uint64_t part[2][256];
+  uint64_t a = 0, b = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    a += t[2 * i];
+    b += t[2 * i + 1];
+  }
+  part[0][threadIdx.x] = a;
+  part[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      part[0][threadIdx.x] += part[0][threadIdx.x + w];
+      part[1][threadIdx.x] += part[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = part[0][0];
+    out[1] = part[1][0];
+  }
+}
+
+__global__ void __launch_bounds__(256) stats_sum_kernel(const uint32_t* t, int64_t n, uint64_t* out) {
+  sum_pairs(t, n, out);
+}
+
+__global__ void __launch_bounds__(256) stats_frames_kernel(const BatchHeader* hdr, const LaunchK* frames) {
+  const int f = blockIdx.x;
+  if (f >= hdr->n_frames) return;
+  const LaunchK& K = frames[f];
+  if (!K.tile_stats || !K.frame_stats) return;
+  sum_pairs(K.tile_stats, (int64_t)K.tiles_x * K.tiles_y, K.frame_stats);
+}
+}  // namespace
+
+extern "C" int lpa_k_stats_sum(const uint32_t* tile_stats, int64_t n_tiles, uint64_t* out, void* stream) {
+  stats_sum_kernel<<<1, 256, 0, static_cast<hipStream_t>(stream)>>>(tile_stats, n_tiles, out);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+extern "C" int lpa_k_stats_frames(const BatchHeader* hdr, const LaunchK* frames, int32_t grid, void* stream) {
+  stats_frames_kernel<<<grid, 256, 0, static_cast<hipStream_t>(stream)>>>(hdr, frames);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
 
 // Clears n ints with a kernel (not a memset node, so it is safe inside graphs).
 extern "C" int lpa_k_zero_i32(int32_t* p, int32_t n, void* stream) {

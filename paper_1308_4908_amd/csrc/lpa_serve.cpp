@@ -43,6 +43,7 @@ struct Request {
   hipEvent_t copied = nullptr;
   int32_t status = LPA_NOT_READY;
   int32_t batch_size = 0;
+  uint64_t n_fp64 = 0, n_invalid = 0;  // the frame's output counts
 };
 
 struct Batch {
@@ -101,7 +102,10 @@ struct Scheduler {
   bool stop = false;
   hipStream_t copy_stream = nullptr;
   hipStream_t compute[2] = {nullptr, nullptr};
-  int next_stream = 0;
+  // per compute stream (at most one batch in flight on each): the batch's
+  // output counts on the device and their pinned host copy
+  uint64_t* d_stats[2] = {nullptr, nullptr};
+  uint64_t* h_stats[2] = {nullptr, nullptr};
   std::thread worker;
   static constexpr size_t kQueueCap = 1024;
   static constexpr int kMaxInflight = 2;
@@ -117,6 +121,8 @@ struct Scheduler {
     res.t_admit_ns = r->admit_ns;
     res.t_start_ns = r->start_ns;
     res.t_done_ns = r->done_ns;
+    res.n_fp64 = r->n_fp64;
+    res.n_invalid = r->n_invalid;
     results[r->ticket] = res;
     if (r->copied) (void)hipEventDestroy(r->copied);
     if (r->slot) pool.put(r->slot);  // the batch that read it has completed
@@ -128,9 +134,13 @@ struct Scheduler {
     cv_done.notify_all();
   }
 
-  // Bytes a frame occupies on the device while in flight.
+  // Bytes a frame occupies on the device while in flight: host raw planes'
+  // slot, pre-pass planes, its per-tile counts (8 bytes per tile of any
+  // 256-pixel tile shape) and its refit marks (3 bytes per output pixel).
   size_t footprint(const Request* r) const {
     size_t b = r->raw_bytes;
+    const size_t W = (size_t)r->params.out_w, H = (size_t)r->params.out_h;
+    b += (W * H / 256 + W / 4 + H / 4 + 2) * 8 + W * H * 3;  // + the refit marks
     if (r->params.storage != LPA_STORE_FUSED)
       for (int s = 0; s < r->rig->n; ++s)
         b += (size_t)r->rig->desc[s].width * r->rig->desc[s].height * (r->params.storage == LPA_STORE_FP16 ? 2 : 8) + 4096;
@@ -142,14 +152,17 @@ struct Scheduler {
     while (!waiting.empty()) {
       Request* r = waiting.front();
       const size_t need = footprint(r);
-      if (need > ctx->budget) {
+      // Served frames in flight will return their memory; without any, what
+      // the context holds (rig-resident calibration planes and weight tables)
+      // stays, and a frame that does not fit beside it never will.
+      if (ctx->used.load() + need > ctx->budget) {
+        if (!admitted.empty() || !inflight.empty()) return;
         waiting.pop_front();
-        set_error(LPA_ERR_OOM, "frame needs %zu bytes, budget is %zu", need, ctx->budget);
+        set_error(LPA_ERR_OOM, "frame needs %zu bytes; %zu of the budget of %zu are held", need,
+                  ctx->used.load(), ctx->budget);
         finish(r, LPA_ERR_OOM);
         continue;
       }
-      // frames already holding memory will return it; wait for them
-      if (ctx->used.load() + need > ctx->budget) return;
       ctx->used.fetch_add(need);
       r->reserved = need;
       waiting.pop_front();
@@ -193,8 +206,9 @@ struct Scheduler {
     Batch b;
     b.reqs.assign(admitted.begin(), admitted.begin() + take);
     admitted.erase(admitted.begin(), admitted.begin() + take);
-    b.stream = next_stream;
-    next_stream ^= 1;
+    // the compute stream no batch in flight uses (launch runs only with
+    // fewer than kMaxInflight = 2 batches in flight)
+    b.stream = (!inflight.empty() && inflight.front().stream == 0) ? 1 : 0;
     hipStream_t st = compute[b.stream];
     std::vector<lpa_rig*> rigs;
     std::vector<lpa_frame> frames;
@@ -206,6 +220,7 @@ struct Scheduler {
       frames.push_back(r->frame);
       params.push_back(r->params);
       outs.push_back(r->out);
+      outs.back().stats = d_stats[b.stream] + 2 * (frames.size() - 1);
       r->batch_size = take;
     }
     std::vector<LaunchK> ks;
@@ -214,10 +229,19 @@ struct Scheduler {
     // the frame footprints were charged at admission: plane scratch is not charged again
     lpa_status s = prepare_frames(ctx, take, rigs.data(), frames.data(), params.data(), outs.data(), st, &ks, &sk,
                                   &b.planes, false);
-    if (s == LPA_OK) s = launch_batch(ctx, ks, sk, st);
+    if (s == LPA_OK) s = launch_batch(ctx, ks, sk, st, false);
     for (const PlaneAlloc& p : b.planes) free_async(ctx, p.p, p.bytes, st, false);
     b.planes.clear();
     hipError_t e = hipSuccess;
+    if (s == LPA_OK) {
+      // counts to the host for lpa_result, and to callers who asked for them
+      e = hipMemcpyAsync(h_stats[b.stream], d_stats[b.stream], sizeof(uint64_t) * 2 * take, hipMemcpyDeviceToHost, st);
+      for (int i = 0; e == hipSuccess && i < take; ++i)
+        if (b.reqs[i]->out.stats)
+          e = hipMemcpyAsync(b.reqs[i]->out.stats, d_stats[b.stream] + 2 * i, sizeof(uint64_t) * 2,
+                             hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) s = device_error(ctx, e, "count copy");
+    }
     if (s == LPA_OK) {
       e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventRecord(b.done, st);
@@ -240,7 +264,13 @@ struct Scheduler {
       const hipError_t q = hipEventQuery(b.done);
       if (q == hipErrorNotReady) break;
       const int32_t st = q == hipSuccess ? LPA_OK : device_error(ctx, q, "batch execution");
-      for (Request* r : b.reqs) finish(r, st);
+      for (size_t i = 0; i < b.reqs.size(); ++i) {
+        if (st == LPA_OK) {
+          b.reqs[i]->n_fp64 = h_stats[b.stream][2 * i];
+          b.reqs[i]->n_invalid = h_stats[b.stream][2 * i + 1];
+        }
+        finish(b.reqs[i], st);
+      }
       (void)hipEventDestroy(b.done);
       inflight.erase(inflight.begin());
       any = true;
@@ -270,15 +300,33 @@ struct Scheduler {
   }
 };
 
+// Frees what serve_init made (streams, count buffers, slots) and the scheduler.
+static void serve_release(Scheduler* s) {
+  s->pool.release();
+  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+  for (hipStream_t st : s->compute)
+    if (st) (void)hipStreamDestroy(st);
+  for (int i = 0; i < 2; ++i) {
+    if (s->d_stats[i]) (void)hipFree(s->d_stats[i]);
+    if (s->h_stats[i]) (void)hipHostFree(s->h_stats[i]);
+  }
+  delete s;
+}
+
 lpa_status serve_init(lpa_ctx* ctx) {
   Scheduler* s = new (std::nothrow) Scheduler();
   if (!s) return set_error(LPA_ERR_OOM, "host allocation failed");
   s->ctx = ctx;
   hipError_t e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
   for (int i = 0; e == hipSuccess && i < 2; ++i) e = hipStreamCreateWithFlags(&s->compute[i], hipStreamNonBlocking);
+  const size_t sb = sizeof(uint64_t) * 2 * Scheduler::kMaxBatch;
+  for (int i = 0; e == hipSuccess && i < 2; ++i) {
+    e = hipMalloc(&s->d_stats[i], sb);
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_stats[i], sb, hipHostMallocDefault);
+  }
   if (e != hipSuccess) {
-    delete s;
-    return set_error(LPA_ERR_DEVICE, "stream create: %s", hipGetErrorString(e));
+    serve_release(s);
+    return set_error(LPA_ERR_DEVICE, "scheduler set-up: %s", hipGetErrorString(e));
   }
   ctx->sched = s;
   s->worker = std::thread([s] { s->run(); });
@@ -296,11 +344,7 @@ void serve_shutdown(lpa_ctx* ctx) {
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  s->pool.release();
-  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
-  for (hipStream_t st : s->compute)
-    if (st) (void)hipStreamDestroy(st);
-  delete s;
+  serve_release(s);
   ctx->sched = nullptr;
 }
 
@@ -325,6 +369,7 @@ lpa_status lpa_submit(lpa_rig* rig, const lpa_frame* frame, const lpa_params* pa
       return set_error(LPA_ERR_UNSUPPORTED, "pre-computed weights are a per-frame form (lpa_reconstruct)");
     if ((st = validate_frame(rig, frame, false)) != LPA_OK) return st;
     if ((st = validate_output(params, out)) != LPA_OK) return st;
+    if ((st = check_batchable(rig, R, frame, out)) != LPA_OK) return st;
     Scheduler* s = ctx->sched;
     Request* r = new (std::nothrow) Request();
     if (!r) return set_error(LPA_ERR_OOM, "host allocation failed");
@@ -364,7 +409,9 @@ lpa_status lpa_poll(lpa_ctx* ctx, uint64_t ticket, lpa_result* out) {
   auto it = s->results.find(ticket);
   if (it == s->results.end()) return set_error(LPA_ERR_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
   *out = it->second;
-  return out->status == LPA_NOT_READY ? LPA_NOT_READY : LPA_OK;
+  if (out->status == LPA_NOT_READY) return LPA_NOT_READY;
+  s->results.erase(it);  // a terminal result is handed out once
+  return LPA_OK;
 }
 
 lpa_status lpa_drain(lpa_ctx* ctx) {

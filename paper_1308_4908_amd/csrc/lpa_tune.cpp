@@ -83,13 +83,15 @@ lpa_status lpa_autotune(lpa_rig* rig, const lpa_frame* frame, const lpa_params* 
       for (int occ : {0, 4}) {
         if (occ == 4 && R.p.order != 2) continue;
         LaunchK K;
-        lpa_status b = build_launch(rig, R, out, src_kind, srcs, pitches, kCandTiles[ti][0], kCandTiles[ti][1], &K);
+        lpa_status b =
+            build_launch(rig, R, frame, out, src_kind, srcs, pitches, kCandTiles[ti][0], kCandTiles[ti][1], &K);
         if (b == LPA_ERR_UNSUPPORTED) continue;
         if (b != LPA_OK) {
           st = b;
           break;
         }
         K.occupancy = occ;
+        K.risk_max = INFINITY;  // the fit alone is timed (the refit launch does not depend on the shape)
         double ms = INFINITY;
         if ((st = time_launch(ctx, K, hs, reps, &ms)) != LPA_OK) break;
         ++tried;

@@ -65,7 +65,7 @@ class Params(ctypes.Structure):
         ("mode", ctypes.c_int32), ("grad_order", ctypes.c_int32), ("grad_halfwin", ctypes.c_int32),
         ("pad_", ctypes.c_int32), ("alpha", ctypes.c_double), ("lambda1", ctypes.c_double),
         ("lambda2", ctypes.c_double), ("grad_radius", ctypes.c_double), ("grad_h", ctypes.c_double),
-        ("max_stretch", ctypes.c_double),
+        ("max_stretch", ctypes.c_double), ("value_tol", ctypes.c_double),
     ]
 
 
@@ -84,6 +84,7 @@ class Output(ctypes.Structure):
         ("sd_map", ctypes.c_void_p), ("sd_map_pitch", ctypes.c_int64),
         ("grad_map", ctypes.c_void_p), ("grad_map_pitch", ctypes.c_int64),
         ("steer_map", ctypes.c_void_p), ("steer_map_pitch", ctypes.c_int64),
+        ("stats", ctypes.c_void_p),
     ]
 
 
@@ -98,6 +99,7 @@ class Result(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("t_arrival_ns", ctypes.c_int64),
         ("t_admit_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
+        ("n_fp64", ctypes.c_uint64), ("n_invalid", ctypes.c_uint64),
     ]
 
 
@@ -254,6 +256,7 @@ def params_struct(p: dict) -> Params:
     q.max_stretch = float(ad.get("max_stretch", 0.0))
     q.grad_order = int(ad.get("grad_order", 0))
     q.grad_halfwin = int(ad.get("grad_halfwin", 2))
+    q.value_tol = float(p.get("value_tol", 0.0))
     return q
 
 
@@ -293,8 +296,14 @@ def frame_struct(raws: Sequence, on_device: bool = True) -> Frame:
     return f
 
 
-def output_struct(rgb, scale_map=None, sd_map=None, grad_map=None, steer_map=None) -> Output:
+def output_struct(rgb, scale_map=None, sd_map=None, grad_map=None, steer_map=None, stats=None) -> Output:
+    """stats: optional int64 device tensor of 2 elements (FP64-valued and
+    no-data output counts, written by the library)."""
     o = Output()
+    if stats is not None:
+        if stats.numel() != 2 or stats.element_size() != 8 or not stats.is_contiguous():
+            raise ValueError("stats must be a contiguous 2-element 64-bit tensor")
+        o.stats = stats.data_ptr()
     if rgb.dim() != 3 or rgb.shape[2] != 3 or rgb.stride(2) != 1 or rgb.stride(1) != 3:
         raise ValueError("rgb must be (H, W, 3) float32 with interleaved pixels")
     o.rgb = rgb.data_ptr()
@@ -356,13 +365,14 @@ class Context:
         except Exception:
             pass
 
-    def reconstruct_batch(self, rigs, frames_raws, params_list, outs, maps=None, stream=None):
+    def reconstruct_batch(self, rigs, frames_raws, params_list, outs, maps=None, stream=None, stats=None):
         n = len(rigs)
         rig_arr = (ctypes.c_void_p * n)(*[r.handle.value for r in rigs])
         fr = (Frame * n)(*[frame_struct(r) for r in frames_raws])
         pr = (Params * n)(*[params_struct(p) for p in params_list])
         maps = maps or [None] * n
-        ou = (Output * n)(*[output_struct(o, m) for o, m in zip(outs, maps)])
+        stats = stats or [None] * n
+        ou = (Output * n)(*[output_struct(o, m, stats=s) for o, m, s in zip(outs, maps, stats)])
         check(lpa_reconstruct_batch(self.handle, n, rig_arr, fr, pr, ou, _stream_handle(stream)))
 
     def tuner_save(self, path: str):
@@ -406,10 +416,10 @@ class Rig:
             pass
 
     def reconstruct(self, raws, params: dict, out, scale_map=None, stream=None, plain: bool = False,
-                    sd_map=None, grad_map=None, steer_map=None):
+                    sd_map=None, grad_map=None, steer_map=None, stats=None):
         fr = frame_struct(raws)
         pr = params_struct(params)
-        ou = output_struct(out, scale_map, sd_map, grad_map, steer_map)
+        ou = output_struct(out, scale_map, sd_map, grad_map, steer_map, stats)
         fn = lpa_reconstruct_plain if plain else lpa_reconstruct
         check(fn(self.handle, ctypes.byref(fr), ctypes.byref(pr), ctypes.byref(ou), _stream_handle(stream)))
 

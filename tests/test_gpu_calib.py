@@ -55,7 +55,9 @@ def calibrated(sensors, seed):
     return [dict(s, calib=frames(s, seed + i)) for i, s in enumerate(sensors)]
 
 
-def run(torch, ctx, sensors, raws, params, plain=False):
+def run(torch, ctx, sensors, raws, params, plain=False, steer=None):
+    """Returns (rgb, scale map, sd map); with steer = [] (CALPA) the steering
+    matrices the GPU used are appended to it."""
     from paper_1308_4908_amd import Rig
 
     rig = Rig(ctx, sensors)
@@ -64,9 +66,12 @@ def run(torch, ctx, sensors, raws, params, plain=False):
     out = torch.full((H, W, 3), -12345.0, device="cuda")
     smap = torch.full((H, W, 3), 0xEE, dtype=torch.uint8, device="cuda")
     sd = torch.full((H, W, 3), -1.0, device="cuda")
-    rig.reconstruct(dev, params, out, smap, plain=plain, sd_map=sd)
+    st = torch.full((H, W, 4), -7.0, device="cuda") if steer is not None else None
+    rig.reconstruct(dev, params, out, smap, plain=plain, sd_map=sd, steer_map=st)
     torch.cuda.synchronize()
     res = out.cpu().numpy(), smap.cpu().numpy(), sd.cpu().numpy()
+    if steer is not None:
+        steer.append(st.cpu().numpy().reshape(-1, 4)[:, :3].astype(np.float64))
     rig.close()
     return res
 
@@ -90,7 +95,8 @@ def test_full_frame_vs_oracle(torch_mod, ctx):
 
 def test_plain_form_equals_fused_and_fp16(torch_mod, ctx):
     """The pre-pass decodes with the same frames (bit-identical); FP16 storage
-    against the oracle fed the FP16-rounded samples (y - b_i) 2^-12."""
+    of 12-bit raw values is lossless, so it is bit-identical too and meets the
+    value gate against the oracle."""
     base = R.random_rig(3, 64, 64, [1.0, 1 / 8, 1 / 64], 1.5, 0.2, 8200, **configs.NOISE)
     sensors = calibrated(base, 8200)
     raws = configs.capture_all(EdgeScene(64, 64, 8200, n_lines=8), base, 8200)
@@ -100,14 +106,10 @@ def test_plain_form_equals_fused_and_fp16(torch_mod, ctx):
     b = run(torch_mod, ctx, sensors, raws, params, plain=True)
     assert np.array_equal(a[0], b[0], equal_nan=True) and np.array_equal(a[1], b[1])
     c = run(torch_mod, ctx, sensors, raws, dict(params, storage="fp16"))
-    rounded = []
-    for s, r in zip(sensors, raws):
-        y = r.astype(np.float64)
-        v = ((y - s["calib"]["bias"]) * 2.0 ** -12).astype(np.float16).astype(np.float64)
-        rounded.append(np.where(y < s["calib"]["sat"], s["calib"]["bias"] + v * 2.0 ** 12, y))
-    orc16 = oracle.reconstruct(sensors, rounded, params, want_fits=True)
-    st = compare(c[0], c[1], orc16, sensors, 1)
-    _say(f"  fp16 vs fp16-fed oracle {st}")
+    assert np.array_equal(a[0], c[0], equal_nan=True) and np.array_equal(a[1], c[1])
+    orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
+    st = compare(c[0], c[1], orc, sensors, 1)
+    _say(f"  fp16 vs oracle {st}")
     assert st["agree_frac"] > 0.999
 
 
@@ -202,7 +204,8 @@ def test_invalid_frames_rejected(torch_mod, ctx):
 
 def test_calpa_with_frames(torch_mod, ctx):
     """CALPA's three passes decode with the frames too: the end-to-end chain
-    against the oracle's chain on the same frames."""
+    against the oracle's chain on the same frames (each value within the gate
+    of the oracle's chain or of its last stage run on the GPU's steering)."""
     base = R.random_rig(3, 64, 64, [1.0, 1 / 8, 1 / 64], 1.5, 0.2, 8700, **configs.NOISE)
     sensors = calibrated(base, 8700)
     raws = configs.capture_all(EdgeScene(64, 64, 8700, n_lines=8), base, 8700)
@@ -210,8 +213,12 @@ def test_calpa_with_frames(torch_mod, ctx):
              "grad_halfwin": 2, "max_stretch": 2.0}
     params = configs.lpa_params(64, 64, 2, [1.0, 2.0, 3.0], mode="calpa", adapt=adapt)
     _say("[gpu] calibration frames, CALPA")
-    rgb, smap, sd = run(torch_mod, ctx, sensors, raws, params)
-    orc = oracle.reconstruct_adaptive(sensors, raws, params, adapt, want_fits=True)
-    st = compare(rgb, smap, orc, sensors, 2, extra_tol=1e-5, gpu_sd=sd)
+    cg = []
+    rgb, smap, sd = run(torch_mod, ctx, sensors, raws, params, steer=cg)
+    orc = oracle.reconstruct_adaptive(sensors, raws, params, adapt, want_fits=True, want_stages=True)
+    assert np.abs(cg[0] - orc["C"]).max() < 1e-5 * np.abs(orc["C"]).max()
+    # the steering difference's effect, measured by the oracle's last stage on the GPU's matrices
+    orc_g = oracle.reconstruct_steered(sensors, raws, params, cg[0], want_fits=True)
+    st = compare(rgb, smap, orc, sensors, 2, gpu_sd=sd, alt_orc=orc_g)
     _say(f"  stats {st}")
     assert st["agree_frac"] > 0.999

@@ -129,16 +129,18 @@ def test_calpa_stages_match_oracle(torch_mod, ctx, case):
 def test_calpa_end_to_end_matches_oracle(torch_mod, ctx):
     """The whole chain against the oracle's own chain (its FP64 gradients and
     steering).  The gradient pass accumulates in FP64, so the two chains'
-    steering matrices agree to a few 1e-6; the values are then held to the
-    isotropic fit's metric and tolerances (conditioning-aware, parity_utils),
-    with 1e-5 relative added for the steering difference."""
+    steering matrices agree to a few 1e-6 (asserted); what that difference
+    does to a value is measured by the oracle's own last stage run on the
+    GPU's steering matrices, and each value must meet the gate against one of
+    the two oracle results (its decisions against the oracle's own chain)."""
     sensors, raws, p = _case(size=64, seed=2400)
     _say("[gpu] calpa end to end")
     g = run_calpa(torch_mod, ctx, sensors, raws, p)
     orc = oracle.reconstruct_adaptive(sensors, raws, p, p["adapt"], want_fits=True, want_stages=True)
     Cg = g["steer"].reshape(-1, 4)[:, :3].astype(np.float64)
     assert np.abs(Cg - orc["C"]).max() < 1e-5 * np.abs(orc["C"]).max()
-    st = compare(g["rgb"], g["map"], orc, sensors, p["order"], extra_tol=1e-5, gpu_sd=g["sd"])
+    orc_g = oracle.reconstruct_steered(sensors, raws, p, Cg, want_fits=True)
+    st = compare(g["rgb"], g["map"], orc, sensors, p["order"], gpu_sd=g["sd"], alt_orc=orc_g)
     _say(f"  end to end {st}")
     assert st["agree_frac"] > 0.999
 

@@ -184,23 +184,39 @@ def test_full_size_sampled(torch_mod, ctx):
 
 
 def test_fp16_storage(torch_mod, ctx):
-    """FP16 normalised-radiance storage: against the oracle fed the same
-    FP16-rounded samples (FP32 tolerance) and against the exact oracle (2e-3)."""
+    """FP16 storage.  Raw values of 12 bits are stored without loss, so the FP16
+    form equals the fused form bit for bit (values, codes and sd) and meets the
+    value gate against the exact oracle.  A 14-bit description of the same data
+    (stored above the black level) is lossy: it is held to the value gate
+    against an oracle fed the same FP16-rounded samples, and to 2e-3 against
+    the exact oracle wherever the storage rounding stays within 1e-3: it moves
+    each stored value, and with it the sample's radiance and inverse variance,
+    by at most 2^-11 relative, so C0 by at most 2^-11 (sum_k |a_k f_k| + sens_y)
+    to first order (sens_y bounds the effect of relative weight changes)."""
     sensors = configs.full_rig(seed=2200, size=128)
     scene = EdgeScene(128, 128, 2200, n_lines=10)
     raws = configs.capture_all(scene, sensors, 2200)
     params = configs.lpa_params(128, 128, 2, [1.0, 2.0, 3.0, 4.0], storage="fp16")
     _say("[gpu] fp16 storage 4 x 128^2 order 2 ICI")
     rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, params)
-    conv = [fp16_round_dn(r, s) for r, s in zip(raws, sensors)]
-    orc16 = oracle.reconstruct([c[1] for c in conv], [c[0] for c in conv], params, want_fits=True)
-    st = compare(rgb, smap, orc16, sensors, 2)
-    _say(f"  vs fp16-fed oracle {st}")
-    assert st["agree_frac"] > 0.999
-    # against the exact oracle: storage rounding moves each radiance sample by at
-    # most 2^-12 relative (half an FP16 ulp), so C0 moves by at most about
-    # 2^-12 sum_k |a_k f_k| (plus the weights' share of the same order)
+    sd16 = LAST_SD[0]
+    rgb_f, smap_f = run_gpu(torch_mod, ctx, sensors, raws, dict(params, storage="fused"))
+    assert np.array_equal(rgb, rgb_f, equal_nan=True) and np.array_equal(smap, smap_f)
+    assert np.array_equal(sd16, LAST_SD[0], equal_nan=True)
     orc = oracle.reconstruct(sensors, raws, params, want_fits=True)
+    st = compare(rgb, smap, orc, sensors, 2, gpu_sd=sd16)
+    _say(f"  12-bit fp16 vs exact oracle {st}")
+    assert st["agree_frac"] > 0.999
+
+    s14 = [dict(s, bit_depth=14) for s in sensors]
+    _say("[gpu] fp16 storage, 14-bit descriptors")
+    rgb, smap = run_gpu(torch_mod, ctx, s14, raws, params)
+    conv = [fp16_round_dn(r, s) for r, s in zip(raws, s14)]
+    assert any(not np.array_equal(c[0][r < 4095], r[r < 4095]) for c, r in zip(conv, raws)), "storage is lossy here"
+    orc16 = oracle.reconstruct([c[1] for c in conv], [c[0] for c in conv], params, want_fits=True)
+    st = compare(rgb, smap, orc16, s14, 2, alt_orc=orc)
+    _say(f"  14-bit fp16 vs fp16-fed oracle (or, for refitted outputs, the exact one) {st}")
+    assert st["agree_frac"] > 0.999
     both = firm_mask(orc, 2, sensors) & firm_mask(orc16, 2, sensors) & (orc["scale_map"] == orc16["scale_map"])
     y = rgb.reshape(-1, 3)[both]
     ref = orc["rgb"][both]
@@ -210,11 +226,13 @@ def test_fp16_storage(torch_mod, ctx):
     chosen = orc["fits"][idx[0], idx[1], (code & 0xF).astype(int), (code >> 4).astype(int)]
     scale = np.maximum(np.abs(ref), floor_of(sensors))
     e = np.abs(y - ref) / scale
-    bound = np.maximum(2e-3 * scale, 4 * 2.0 ** -12 * chosen["l1f"] + 64 * 2.0 ** -24 * chosen["sens_y"])
-    r = (np.abs(y - ref) / (2.0 ** -12 * np.maximum(chosen["l1f"], 1e-300)))[ok]
-    _say(f"  vs exact oracle: max rel {e[ok].max():.3e} p50 {np.median(e[ok]):.3e}; "
-         f"within 2e-3: {np.mean(e[ok] <= 2e-3):.6f}; max |err| / (2^-12 S1) {r.max():.3f}")
-    assert np.all(np.abs(y - ref)[ok] <= bound[ok])
+    storage = 2.0 ** -11 * (chosen["l1f"] + chosen["sens_y"])
+    quiet = ok & (storage <= 1e-3 * scale)
+    _say(f"  14-bit fp16 vs exact oracle: {np.count_nonzero(quiet)} of {np.count_nonzero(ok)} values where "
+         f"storage rounding stays within 1e-3" + (f": max e {e[quiet].max():.3e}" if quiet.any() else "") +
+         f"; all values: max e {e[ok].max():.3e}, above 2e-3: {np.count_nonzero(e[ok] > 2e-3)}")
+    assert np.all(e[quiet] <= 2e-3)
+    assert np.all(np.abs(y - ref)[ok] <= 2e-3 * scale[ok] + 2 * storage[ok])
 
 
 def test_resampled_output(torch_mod, ctx):
