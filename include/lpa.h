@@ -276,6 +276,21 @@ lpa_status lpa_destroy_rig(lpa_rig* rig);
 lpa_status lpa_reconstruct(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
                            const lpa_output* out, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * reconstruction as lpa_reconstruct (same kernels, same tuned launch shape,
+ * bit-identical results) for mode LPA with storage FUSED, with every scratch
+ * buffer in a static 16 MiB device array per GPU instead of the context's
+ * stream-ordered allocations.  It calls no hipMalloc / hipFree.  The array
+ * holds the refit marks (3 bytes per output pixel) and, if out->stats is set,
+ * the per-tile counts (8 bytes per tile): outputs beyond about 5.5 Mpixel
+ * return LPA_ERR_UNSUPPORTED, as do CALPA, the pre-pass storage forms and
+ * LPA_FLAG_PRECOMPUTED_WEIGHTS.  Every call on one GPU shares its array:
+ * calls that overlap on one GPU (other streams, other threads) race and must
+ * be serialised by the caller. */
+lpa_status lpa_reconstruct_noalloc(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
+                                   const lpa_output* out, void* hip_stream);
+
 /* The plain per-frame form: FP32 radiance / inverse-variance planes from a
  * separate pre-pass launch, then one fit launch with 16x16 tiles (no tuning;
  * smaller tiles only where the LDS rule above requires them).  Same results

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblpa.so")
 PEAK_PROBE = os.path.join(HERE, "peak_probe")  # vector-ALU ceiling measurement (bench.py --peak-probe)
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["lpa_kernels.hip", "lpa_api.cpp", "lpa_batch.cpp", "lpa_serve.cpp", "lpa_tune.cpp", "lpa_stencil.cpp"]
+SOURCES = ["lpa_kernels.hip", "lpa_api.cpp", "lpa_batch.cpp", "lpa_serve.cpp", "lpa_tune.cpp", "lpa_stencil.cpp",
+           "lpa_noalloc.cpp"]
 ARCH = os.environ.get("LPA_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

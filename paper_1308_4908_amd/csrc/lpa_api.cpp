@@ -703,7 +703,8 @@ lpa_status lpa_create_ctx(int device, size_t hbm_budget_bytes, lpa_ctx** out) {
   size_t free_b = 0, total_b = 0;
   (void)hipMemGetInfo(&free_b, &total_b);
   ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
-  lpa_status st = ctx_init_runtime(ctx);
+  lpa_status st = noalloc_init_device(device);
+  if (st == LPA_OK) st = ctx_init_runtime(ctx);
   if (st != LPA_OK) {
     delete ctx;
     return st;

@@ -212,6 +212,9 @@ lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_f
 // Whether a frame can join a batch: some 256-lane tile shape stages its
 // windows (LPA_ERR_UNSUPPORTED with the reason otherwise).
 lpa_status check_batchable(const lpa_rig* rig, const Resolved& R, const lpa_frame* frame, const lpa_output* out);
+// Device address of the allocation-free entry point's static scratch on the
+// current device (lpa_noalloc.cpp); called by lpa_create_ctx.
+lpa_status noalloc_init_device(int device);
 lpa_status serve_init(lpa_ctx* ctx);
 void serve_shutdown(lpa_ctx* ctx);
 

@@ -116,6 +116,8 @@ SIGNATURES = {
                                          ctypes.POINTER(Output), ctypes.c_void_p]),
     "lpa_reconstruct_plain": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Frame), ctypes.POINTER(Params),
                                                ctypes.POINTER(Output), ctypes.c_void_p]),
+    "lpa_reconstruct_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Frame), ctypes.POINTER(Params),
+                                                 ctypes.POINTER(Output), ctypes.c_void_p]),
     "lpa_reconstruct_batch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
                                                ctypes.POINTER(Frame), ctypes.POINTER(Params),
                                                ctypes.POINTER(Output), ctypes.c_void_p]),
@@ -173,6 +175,7 @@ lpa_destroy_rig = _c("lpa_destroy_rig")
 lpa_reconstruct = _c("lpa_reconstruct")
 lpa_reconstruct_plain = _c("lpa_reconstruct_plain")
 lpa_reconstruct_batch = _c("lpa_reconstruct_batch")
+lpa_reconstruct_noalloc = _c("lpa_reconstruct_noalloc")
 lpa_submit = _c("lpa_submit")
 lpa_poll = _c("lpa_poll")
 lpa_drain = _c("lpa_drain")
@@ -416,11 +419,13 @@ class Rig:
             pass
 
     def reconstruct(self, raws, params: dict, out, scale_map=None, stream=None, plain: bool = False,
-                    sd_map=None, grad_map=None, steer_map=None, stats=None):
+                    sd_map=None, grad_map=None, steer_map=None, stats=None, noalloc: bool = False):
+        """plain: the plain per-frame FP32 form; noalloc: the allocation-free
+        entry point (fused LPA, static scratch)."""
         fr = frame_struct(raws)
         pr = params_struct(params)
         ou = output_struct(out, scale_map, sd_map, grad_map, steer_map, stats)
-        fn = lpa_reconstruct_plain if plain else lpa_reconstruct
+        fn = lpa_reconstruct_plain if plain else (lpa_reconstruct_noalloc if noalloc else lpa_reconstruct)
         check(fn(self.handle, ctypes.byref(fr), ctypes.byref(pr), ctypes.byref(ou), _stream_handle(stream)))
 
     def autotune(self, raws, params: dict, out, reps: int = 3, stream=None) -> TuneResult:
