@@ -191,7 +191,7 @@ typedef struct {
    * are accumulated in FP32; with every fit the kernel computes a bound S on
    * how far the rounding of its moment terms can move C0 (per unit relative
    * rounding; an upper estimate of the componentwise condition of C0 in the
-   * moment terms), and where 16 * 2^-24 * S exceeds value_tol times the scale
+   * moment terms), and where 8 * 2^-24 * S exceeds value_tol times the scale
    * above, the chosen fit of that output is recomputed from FP64 products
    * and sums of the same samples.  In HDR windows C0 is often a small
    * difference of large terms, so a few percent of the outputs of the

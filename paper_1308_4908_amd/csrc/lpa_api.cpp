@@ -226,6 +226,7 @@ void rig_constants(const lpa_sensor_desc& S, SensorK* k) {
   k->sat = (float)S.saturation;
   k->gain64 = S.gain;
   k->ge64 = ge;
+  k->inv_ge64 = 1.0 / ge;
   k->black64 = S.black_level;
   k->read_var64 = S.read_sigma * S.read_sigma;
   k->sat64 = S.saturation;
@@ -257,6 +258,11 @@ constexpr int64_t kStaticLdsReserve = 256;
 
 // Default accuracy target of the output values (lpa_params.value_tol = 0).
 constexpr double kDefaultValueTol = 1e-4;
+// |dC0| <= kRoundingFactor u S for the FP32 fit, S its rounding bound: each
+// moment term goes through a few roundings (products, then the running sum);
+// an FP32 emulation of the fit on the full workload's supports gave at most
+// 5.5 u times the componentwise condition, which S bounds from above.
+constexpr double kRoundingFactor = 8.0;
 
 // Fill the launch-dependent parts of a descriptor.  Returns false if the
 // LDS footprint of the requested tile does not fit.
@@ -283,13 +289,12 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_frame* 
   K->tau_fp64 = (float)R.tau_fp64;
   K->use_fp64 = (p.flags & LPA_FLAG_NO_FP64_FALLBACK) ? 0 : 1;
   // FP64 values where the FP32 moments' rounding bound exceeds the target:
-  // 16 u S > value_tol * max(|C0|, floor), u = 2^-24 (the factor 16 covers the
-  // rounding of the products and partial sums each moment term goes through)
+  // kRoundingFactor u S > value_tol * max(|C0|, floor), u = 2^-24.
   double ge_max = 0;
   for (int s = 0; s < rig->n; ++s) ge_max = std::max(ge_max, rig->desc[s].gain * rig->desc[s].exposure);
   K->value_floor = (float)(1.0 / ge_max);
   const double vtol = p.value_tol == 0 ? kDefaultValueTol : p.value_tol;
-  K->risk_max = (vtol < 0 || !K->use_fp64) ? INFINITY : (float)(vtol / (16.0 * std::ldexp(1.0, -24)));
+  K->risk_max = (vtol < 0 || !K->use_fp64) ? INFINITY : (float)(vtol / (kRoundingFactor * std::ldexp(1.0, -24)));
   K->rgb = out->rgb;
   K->rgb_pitch = out->row_pitch_bytes;
   K->map = out->scale_map;

@@ -172,8 +172,9 @@ lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks_in, int src
   return st;
 }
 
-// Copy the table into a slot and replay (or capture) its graph: the table
-// copy, the queue reset, the persistent kernel and the count reduction.
+// Copy the table into a slot and replay (or build) its graph: the table copy,
+// the queue reset, the persistent kernel, the FP64 refit and the count
+// reduction.
 lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, int block, int lds, int grid,
                         int64_t total, hipStream_t stream) {
   const int n = (int)ks.size();
@@ -217,19 +218,11 @@ lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
     }
     char* d = static_cast<char*>(sl.d_buf);
     hipGraph_t graph = nullptr;
-    if ((e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-      return device_error(ctx, e, "begin capture");
-    (void)hipMemcpyAsync(d, h, L.copy_bytes, hipMemcpyHostToDevice, ctx->capture_stream);
-    int32_t* q = reinterpret_cast<int32_t*>(d + L.queue_off);
-    (void)lpa_k_zero_i32(q, 8, ctx->capture_stream);  // one tile counter per XCD range
-    (void)lpa_k_fit_batch(reinterpret_cast<const BatchHeader*>(d), reinterpret_cast<const LaunchK*>(d + L.frames_off),
-                          reinterpret_cast<const int64_t*>(d + L.first_off), q, src_kind, block, lds, grid,
-                          ctx->capture_stream);
-    (void)lpa_k_refit_batch(reinterpret_cast<const BatchHeader*>(d), reinterpret_cast<const LaunchK*>(d + L.frames_off),
-                            reinterpret_cast<const int64_t*>(d + L.first_off), ctx->n_cu * 8, ctx->capture_stream);
-    (void)lpa_k_stats_frames(reinterpret_cast<const BatchHeader*>(d), reinterpret_cast<const LaunchK*>(d + L.frames_off),
-                             sl.cap, ctx->capture_stream);
-    if ((e = hipStreamEndCapture(ctx->capture_stream, &graph)) != hipSuccess) return device_error(ctx, e, "end capture");
+    if (lpa_k_batch_graph(&graph, d, h, L.copy_bytes, reinterpret_cast<const BatchHeader*>(d),
+                          reinterpret_cast<const LaunchK*>(d + L.frames_off),
+                          reinterpret_cast<const int64_t*>(d + L.first_off), reinterpret_cast<int32_t*>(d + L.queue_off),
+                          src_kind, block, lds, grid, ctx->n_cu * 8, sl.cap) != 0)
+      return device_error(ctx, hipGetLastError(), "batch graph");
     e = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
@@ -245,8 +238,7 @@ lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
 }
 
 lpa_status ctx_init_runtime(lpa_ctx* ctx) {
-  hipError_t e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
-  if (e != hipSuccess) return set_error(LPA_ERR_DEVICE, "stream create: %s", hipGetErrorString(e));
+  hipError_t e;
   ctx->slots.resize(4);
   for (BatchSlot& sl : ctx->slots)
     if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess)
@@ -263,8 +255,6 @@ void ctx_shutdown_runtime(lpa_ctx* ctx) {
     if (sl.done) (void)hipEventDestroy(sl.done);
   }
   ctx->slots.clear();
-  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
-  ctx->capture_stream = nullptr;
 }
 
 }  // namespace lpa

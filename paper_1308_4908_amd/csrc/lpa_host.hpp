@@ -91,9 +91,9 @@ class Tuner {
   std::map<TuneKey, TuneChoice> table_;
 };
 
-// One reusable batch table: pinned host staging, device copy, the captured
-// graph that copies it and runs the persistent kernel, and an event marking
-// the end of its last use.
+// One reusable batch table: pinned host staging, device copy, the graph that
+// copies it and runs the batch's kernels, and an event marking the end of its
+// last use.
 struct BatchSlot {
   void* h_buf = nullptr;
   void* d_buf = nullptr;
@@ -127,11 +127,10 @@ struct lpa_ctx {
   std::atomic<size_t> used{0};
   std::atomic<bool> failed{false};
   lpa::Tuner tuner;
-  // batch path: a ring of reusable tables and a stream used only for capture
+  // batch path: a ring of reusable tables, each with its graph
   std::mutex batch_mu;
   std::vector<lpa::BatchSlot> slots;
   int next_slot = 0;
-  hipStream_t capture_stream = nullptr;
   // serving
   lpa::Scheduler* sched = nullptr;
   // live rigs (destroyed with the context)

@@ -5,6 +5,8 @@
 
 #include <stdint.h>
 
+#include <hip/hip_runtime.h>
+
 namespace lpa {
 
 constexpr int kMaxSensors = 8;
@@ -51,7 +53,7 @@ struct SensorK {
   int64_t raw_pitch;    // bytes
   int32_t raw_f32;      // raw samples are float DN (else uint16)
   int32_t pad2_;
-  double gain64, ge64;  // g, g n
+  double gain64, ge64, inv_ge64;  // g, g n, 1 / (g n)
   double black64, read_var64, sat64;
 };
 
@@ -202,7 +204,15 @@ int lpa_k_refit(const lpa::LaunchK* k, void* stream);
 // The same for a batch table (after the persistent fit; grid workgroups loop
 // over the batch's tiles).
 int lpa_k_refit_batch(const lpa::BatchHeader* hdr, const lpa::LaunchK* frames, const int64_t* first_tile,
-                      int32_t grid, void* stream);
+                      int32_t grid, int32_t lds_floats2, void* stream);
+// The graph of one batch, built node by node: copy of the table (copy_bytes
+// from pinned h_table to d_table, which holds d_hdr / d_frames / d_first),
+// queue reset, persistent fit (grid x block, lds_floats2 float2 of LDS), FP64
+// refit (refit_grid workgroups) and count reduction (cap workgroups).
+int lpa_k_batch_graph(hipGraph_t* out, void* d_table, const void* h_table, size_t copy_bytes,
+                      const lpa::BatchHeader* d_hdr, const lpa::LaunchK* d_frames, const int64_t* d_first,
+                      int32_t* d_queue, int32_t src_kind, int32_t block, int32_t lds_floats2, int32_t grid,
+                      int32_t refit_grid, int32_t cap);
 // Zero n ints with a small kernel (graph-safe replacement for a memset).
 int lpa_k_zero_i32(int32_t* p, int32_t n, void* stream);
 // Sum a frame's per-tile counts (n_tiles pairs) into out[0], out[1].

@@ -758,6 +758,17 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
   }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i runs on
+// XCD i mod 8), each with its own L2.  Giving XCD x a contiguous range of
+// tiles keeps the halo a tile shares with its neighbours in that XCD's L2
+// instead of fetching it from HBM once per XCD.  A bijection on [0, n).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int i, int n) {
+  const int q = n / kXcds, r = n - q * kXcds;
+  const int x = i % kXcds, j = i / kXcds;
+  return x * q + (x < r ? x : r) + j;
+}
+
 // ---------------------------------------------------------------------------
 // FP64 refit from the raw frame.  Outputs whose FP32 value could be off by
 // more than the target are recomputed as the model defines them, in FP64
@@ -769,22 +780,52 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
 // FP32 rounding of a sample's position or weight moves it by more than the
 // target, so the refit keeps nothing of the FP32 pass but its decision.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool decode64(const SensorK& S, int x, int y, double& f, double& iv) {
-  const char* row = static_cast<const char*>(S.raw) + (int64_t)y * S.raw_pitch;
-  const double dn = S.raw_f32 ? (double)reinterpret_cast<const float*>(row)[x]
-                              : (double)reinterpret_cast<const uint16_t*>(row)[x];
-  double b = S.black64, a = 1.0, rv = S.read_var64, sat = S.sat64;
+// 1 / x to FP64 accuracy: the hardware reciprocal and one Newton step.
+__device__ __forceinline__ double rcp64(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+
+// exp(-t) for t >= 0 in FP64 (relative error ~1e-15): with x = -t log2(e) =
+// n + r, n = rint(x), |r| <= 1/2, exp(-t) = 2^n exp(r ln 2), and exp(s),
+// |s| <= ln(2) / 2, from its Taylor series to degree 12 (remainder below
+// 0.35^13 / 13! ~ 2e-16), evaluated by Horner's rule.
+__device__ __forceinline__ double exp_neg64(double t) {
+  const double x = -t * 1.4426950408889634;
+  const double n = __builtin_rint(x);
+  const double s = (x - n) * 0.6931471805599453;
+  double p = 1.0 / 479001600.0;  // 1 / 12!
+  p = __builtin_fma(p, s, 1.0 / 39916800.0);
+  p = __builtin_fma(p, s, 1.0 / 3628800.0);
+  p = __builtin_fma(p, s, 1.0 / 362880.0);
+  p = __builtin_fma(p, s, 1.0 / 40320.0);
+  p = __builtin_fma(p, s, 1.0 / 5040.0);
+  p = __builtin_fma(p, s, 1.0 / 720.0);
+  p = __builtin_fma(p, s, 1.0 / 120.0);
+  p = __builtin_fma(p, s, 1.0 / 24.0);
+  p = __builtin_fma(p, s, 1.0 / 6.0);
+  p = __builtin_fma(p, s, 0.5);
+  p = __builtin_fma(p, s, 1.0);
+  p = __builtin_fma(p, s, 1.0);
+  return n < -1060.0 ? 0.0 : __builtin_amdgcn_ldexp(p, (int)n);
+}
+
+// Radiance and inverse variance of raw value dn at sensor pixel i (row-major
+// index) in FP64: f = (dn - b) / (g n a), Var f = (g max(f, 0) + Var[r] / (g n a))
+// / (g n a), with the pixel's calibration frames where the sensor has them.
+// Returns false where the sample is masked.
+__device__ __forceinline__ bool decode64(const SensorK& S, int64_t i, double dn, double& f, double& iv) {
+  double b = S.black64, rv = S.read_var64, sat = S.sat64, inv_ga = S.inv_ge64;
   if (S.calib) {
-    const float4 c = S.calib[(int64_t)y * S.width + x];
+    const float4 c = S.calib[i];
     b = c.x;
-    a = c.y;
+    inv_ga *= rcp64((double)c.y);
     rv = c.z;
     sat = c.w;
   }
   if (!(dn < sat)) return false;
-  const double ga = S.ge64 * a;
-  f = (dn - b) / ga;
-  iv = (ga * ga) / (S.gain64 * ga * fmax(f, 0.0) + rv);
+  f = (dn - b) * inv_ga;
+  iv = rcp64(inv_ga * __builtin_fma(S.gain64, fmax(f, 0.0), rv * inv_ga));
   return true;
 }
 
@@ -823,18 +864,20 @@ __device__ __forceinline__ void acc64_d(Acc64<ORDER>& a, double x, double y, dou
 }
 
 // C0 of output pixel (u, v), channel c, at radius index m and order o (<=
-// ORDER), in FP64 from the raw frame; steered windows read the pixel's
-// steering matrix.  Every sensor's box covers the window: the disc of radius
+// ORDER), in FP64 from the raw frame (its samples staged in LDS, `raw` with
+// the tile's regions `regs`); steered windows read the pixel's steering
+// matrix.  Every sensor's box covers the window: the disc of radius
 // r' (the ellipse d^T C d < r'^2, whose half-width along a sensor axis with
 // inverse-map row a is r' sqrt(a^T C^-1 a)).  One lane per output.
-template <int ORDER, bool STEER>
-__device__ double refit_one(const LaunchK& K, int u, int v, int c, int o, int m) {
+template <int ORDER, bool STEER, typename RawT>
+__device__ double refit_one(const LaunchK& K, const RawT* raw, const Region* regs, int u, int v, int c, int o,
+                            int m) {
   const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
   const double Yj = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
   const int cls = (c == 1) ? 1 : 0;
   const double r = K.sc[m].radius[cls];
   const double r2 = r * r, ih = 1.0 / K.sc[m].h[cls];
-  const double ee = exp(-r2 * ih);
+  const double ee = exp_neg64(r2 * ih);
   double cxx = 1.0, cxy = 0.0, cyy = 1.0, ixx = 1.0, ixy = 0.0, iyy = 1.0;  // C and C^-1
   if constexpr (STEER) {
     const float4 q = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(K.steer) +
@@ -851,6 +894,8 @@ __device__ double refit_one(const LaunchK& K, int u, int v, int c, int o, int m)
   acc64_zero(a);
   for (int s = 0; s < K.n_sensors; ++s) {
     const SensorK& S = K.s[s];
+    const Region R = regs[s];
+    const RawT* plane = raw + S.lds_off;
     const double px = S.inv[0] * Xj + S.inv[1] * Yj + S.inv[2];
     const double py = S.inv[3] * Xj + S.inv[4] * Yj + S.inv[5];
     const double ax = S.inv[0], ay = S.inv[1], bx = S.inv[3], by = S.inv[4];
@@ -864,6 +909,7 @@ __device__ double refit_one(const LaunchK& K, int u, int v, int c, int o, int m)
       for (int j = 0; j < ny; ++j) {
         const int y = yb + 2 * j;
         if (y < 0 || y >= S.height) continue;
+        const RawT* row = plane + (y - R.y0) * R.w - R.x0;
         for (int i = 0; i < nx; ++i) {
           const int x = xb + 2 * i;
           if (x < 0 || x >= S.width) continue;
@@ -872,7 +918,8 @@ __device__ double refit_one(const LaunchK& K, int u, int v, int c, int o, int m)
           const double d2 = STEER ? cxx * dX * dX + 2.0 * cxy * dX * dY + cyy * dY * dY : dX * dX + dY * dY;
           if (!(d2 < r2)) continue;
           double f, iv;
-          if (decode64(S, x, y, f, iv)) acc64_d<ORDER>(a, dX, dY, f, (exp(-d2 * ih) - ee) * iv);
+          if (decode64(S, (int64_t)y * S.width + x, (double)row[x], f, iv))
+            acc64_d<ORDER>(a, dX, dY, f, (exp_neg64(d2 * ih) - ee) * iv);
         }
       }
     }
@@ -889,54 +936,114 @@ __device__ double refit_one(const LaunchK& K, int u, int v, int c, int o, int m)
   return y;
 }
 
-// The refit of one tile: its marked outputs are gathered in LDS, then each
-// lane of the workgroup takes one.
-template <int ORDER, bool STEER>
-__device__ __forceinline__ void refit_tile(const LaunchK& K, int tile, uint16_t* list, int* count) {
+// The refit of one tile: its marked outputs are gathered in LDS ordered by
+// (channel, radius) -- a counting sort, so the lanes of a wave mostly walk
+// boxes of one shape -- then each lane of the workgroup takes one.
+constexpr int kRefitClasses = 3 * kMaxScales;
+constexpr int kRefitBlock = 64;  // one wave per tile
+
+template <int ORDER, bool STEER, typename RawT>
+__device__ __forceinline__ void refit_tile(const LaunchK& K, int tile, uint16_t* list, int* count, RawT* raw,
+                                           Region* regs) {
   const int u0 = (tile % K.tiles_x) * K.tile_w, v0 = (tile / K.tiles_x) * K.tile_h;
   const int n_out = K.tile_w * K.tile_h * 3;
-  if (threadIdx.x == 0) *count = 0;
-  __syncthreads();
-  for (int t = threadIdx.x; t < n_out; t += blockDim.x) {
+  for (int k = threadIdx.x; k <= kRefitClasses; k += blockDim.x) count[k] = 0;
+  // each lane holds the codes of outputs t = threadIdx.x + k * kRefitBlock
+  constexpr int kCodes = 768 / kRefitBlock;
+  uint8_t codes[kCodes];
+#pragma unroll
+  for (int k = 0; k < kCodes; ++k) {
+    const int t = threadIdx.x + k * kRefitBlock;
     const int p = t / 3, c = t - 3 * p;
     const int u = u0 + p % K.tile_w, v = v0 + p / K.tile_w;
-    if (u < K.out_w && v < K.out_h && (K.refit_map[(int64_t)v * K.refit_pitch + 3 * u + c] & 0x80))
-      list[atomicAdd(count, 1)] = (uint16_t)t;
+    codes[k] = (t < n_out && u < K.out_w && v < K.out_h) ? K.refit_map[(int64_t)v * K.refit_pitch + 3 * u + c] : 0;
   }
   __syncthreads();
-  const int n = *count;
+#pragma unroll
+  for (int k = 0; k < kCodes; ++k) {
+    const int t = threadIdx.x + k * kRefitBlock;
+    if (codes[k] & 0x80) atomicAdd(&count[1 + (t % 3) * kMaxScales + (codes[k] & 7)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 1; k <= kRefitClasses; ++k) count[k] += count[k - 1];  // count[k]: start of class k
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kCodes; ++k) {
+    const int t = threadIdx.x + k * kRefitBlock;
+    if (codes[k] & 0x80) list[atomicAdd(&count[(t % 3) * kMaxScales + (codes[k] & 7)], 1)] = (uint16_t)t;
+  }
+  __syncthreads();
+  const int n = count[kRefitClasses - 1];
+  if (n == 0) return;  // workgroup-uniform
+  // the tile's raw samples (the fit's regions, which hold every box), read
+  // kStageRun per lane at a time so that their loads are in flight together
+  constexpr int kStageRun = 8;
+  for (int s = 0; s < K.n_sensors; ++s) {
+    const SensorK& S = K.s[s];
+    const Region r = tile_region(K, S, u0, v0);
+    if (threadIdx.x == 0) regs[s] = r;
+    RawT* dst = raw + S.lds_off;
+    const int total = r.w * r.h;
+    for (int e0 = threadIdx.x; e0 < total; e0 += kStageRun * kRefitBlock) {
+      RawT val[kStageRun];
+#pragma unroll
+      for (int k = 0; k < kStageRun; ++k) {
+        const int e = e0 + k * kRefitBlock;
+        const int row = e / r.w, col = e - row * r.w;
+        const int x = r.x0 + col, y = r.y0 + row;
+        val[k] = RawT(0);
+        if (e < total && x >= 0 && y >= 0 && x < S.width && y < S.height)
+          val[k] = reinterpret_cast<const RawT*>(static_cast<const char*>(S.raw) + (int64_t)y * S.raw_pitch)[x];
+      }
+#pragma unroll
+      for (int k = 0; k < kStageRun; ++k)
+        if (e0 + k * kRefitBlock < total) dst[e0 + k * kRefitBlock] = val[k];
+    }
+  }
+  __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int t = list[i];
     const int p = t / 3, c = t - 3 * p;
     const int u = u0 + p % K.tile_w, v = v0 + p / K.tile_w;
     const int code = K.refit_map[(int64_t)v * K.refit_pitch + 3 * u + c];
-    const double y = refit_one<ORDER, STEER>(K, u, v, c, (code >> 4) & 3, code & 7);
+    const double y = refit_one<ORDER, STEER>(K, raw, regs, u, v, c, (code >> 4) & 3, code & 7);
     float* orow = reinterpret_cast<float*>(reinterpret_cast<char*>(K.rgb) + (int64_t)v * K.rgb_pitch);
     orow[3 * u + c] = (float)y;
   }
   __syncthreads();
 }
 
-constexpr int kRefitBlock = 64;
-
-template <int ORDER, bool STEER>
+// One workgroup per tile; dynamic LDS: the raw samples of the tile's regions
+// (K.lds_floats2 elements of RawT: uint16 frames as uint16, float DN as float).
+template <int ORDER, bool STEER, typename RawT>
 __global__ void __launch_bounds__(kRefitBlock) refit_kernel(const LaunchK K) {
+  extern __shared__ float2 lds[];
   __shared__ uint16_t list[768];
-  __shared__ int count;
-  refit_tile<ORDER, STEER>(K, blockIdx.x, list, &count);
+  __shared__ int count[kRefitClasses + 1];
+  __shared__ Region regs[kMaxSensors];
+  refit_tile<ORDER, STEER, RawT>(K, xcd_tile(blockIdx.x, gridDim.x), list, count, reinterpret_cast<RawT*>(lds),
+                                 regs);
 }
 
 // Batch form: workgroups take tiles t = blockIdx.x, blockIdx.x + gridDim.x, ...
-template <int ORDER>
-__device__ __forceinline__ void refit_batch_tile(const LaunchK& K, int local, uint16_t* list, int* count) {
-  refit_tile<ORDER, false>(K, local, list, count);
+template <typename RawT>
+__device__ __forceinline__ void refit_batch_frame(const LaunchK& K, int local, uint16_t* list, int* count,
+                                                  RawT* raw, Region* regs) {
+  switch (K.order) {
+    case 0: refit_tile<0, false, RawT>(K, local, list, count, raw, regs); break;
+    case 1: refit_tile<1, false, RawT>(K, local, list, count, raw, regs); break;
+    default: refit_tile<2, false, RawT>(K, local, list, count, raw, regs); break;
+  }
 }
 
 __global__ void __launch_bounds__(kRefitBlock) refit_batch_kernel(const BatchHeader* __restrict__ hdr,
                                                                   const LaunchK* __restrict__ frames,
                                                                   const int64_t* __restrict__ first_tile) {
+  extern __shared__ float2 lds[];
   __shared__ uint16_t list[768];
-  __shared__ int count;
+  __shared__ int count[kRefitClasses + 1];
+  __shared__ Region regs[kMaxSensors];
   const int n_frames = hdr->n_frames;
   const int64_t total = hdr->total_tiles;
   for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
@@ -949,11 +1056,8 @@ __global__ void __launch_bounds__(kRefitBlock) refit_batch_kernel(const BatchHea
     const LaunchK& K = frames[f];
     if (!K.refit_map) continue;
     const int local = (int)(t - first_tile[f]);
-    switch (K.order) {
-      case 0: refit_batch_tile<0>(K, local, list, &count); break;
-      case 1: refit_batch_tile<1>(K, local, list, &count); break;
-      default: refit_batch_tile<2>(K, local, list, &count); break;
-    }
+    if (K.s[0].raw_f32) refit_batch_frame<float>(K, local, list, count, reinterpret_cast<float*>(lds), regs);
+    else refit_batch_frame<uint16_t>(K, local, list, count, reinterpret_cast<uint16_t*>(lds), regs);
   }
 }
 
@@ -1270,16 +1374,6 @@ __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2*
   }
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i runs on
-// XCD i mod 8), each with its own L2.  Giving XCD x a contiguous range of
-// tiles keeps the halo a tile shares with its neighbours in that XCD's L2
-// instead of fetching it from HBM once per XCD.  A bijection on [0, n).
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_tile(int i, int n) {
-  const int q = n / kXcds, r = n - q * kXcds;
-  const int x = i % kXcds, j = i / kXcds;
-  return x * q + (x < r ? x : r) + j;
-}
 
 // Compiled for at least 3 waves per SIMD (<= 168 VGPRs).
 template <int ORDER, bool ICI, int SRC>
@@ -1791,21 +1885,28 @@ extern "C" int lpa_k_refit(const LaunchK* k, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const dim3 grid(K.tiles_x * K.tiles_y), block(kRefitBlock);
   const bool steer = K.steer != nullptr;
+  const bool f32 = K.s[0].raw_f32 != 0;
+  const size_t lds = (size_t)K.lds_floats2 * (f32 ? 4 : 2);
+#define LPA_REFIT(O, ST)                                                          \
+  (f32 ? (refit_kernel<O, ST, float><<<grid, block, lds, st>>>(K), 0)          \
+       : (refit_kernel<O, ST, uint16_t><<<grid, block, lds, st>>>(K), 0))
   switch (K.order * 2 + (steer ? 1 : 0)) {
-    case 0: refit_kernel<0, false><<<grid, block, 0, st>>>(K); break;
-    case 1: refit_kernel<0, true><<<grid, block, 0, st>>>(K); break;
-    case 2: refit_kernel<1, false><<<grid, block, 0, st>>>(K); break;
-    case 3: refit_kernel<1, true><<<grid, block, 0, st>>>(K); break;
-    case 4: refit_kernel<2, false><<<grid, block, 0, st>>>(K); break;
-    case 5: refit_kernel<2, true><<<grid, block, 0, st>>>(K); break;
+    case 0: LPA_REFIT(0, false); break;
+    case 1: LPA_REFIT(0, true); break;
+    case 2: LPA_REFIT(1, false); break;
+    case 3: LPA_REFIT(1, true); break;
+    case 4: LPA_REFIT(2, false); break;
+    case 5: LPA_REFIT(2, true); break;
     default: return -1;
   }
+#undef LPA_REFIT
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 extern "C" int lpa_k_refit_batch(const BatchHeader* hdr, const LaunchK* frames, const int64_t* first_tile,
-                                 int32_t grid, void* stream) {
-  refit_batch_kernel<<<grid, kRefitBlock, 0, static_cast<hipStream_t>(stream)>>>(hdr, frames, first_tile);
+                                 int32_t grid, int32_t lds_floats2, void* stream) {
+  const size_t lds = (size_t)lds_floats2 * 4;
+  refit_batch_kernel<<<grid, kRefitBlock, lds, static_cast<hipStream_t>(stream)>>>(hdr, frames, first_tile);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -1815,6 +1916,8 @@ __global__ void zero_i32_kernel(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 }  // namespace
+
+
 
 namespace {
 // One workgroup of 256 threads sums n pairs of per-tile counts.
@@ -1868,4 +1971,62 @@ extern "C" int lpa_k_stats_frames(const BatchHeader* hdr, const LaunchK* frames,
 extern "C" int lpa_k_zero_i32(int32_t* p, int32_t n, void* stream) {
   zero_i32_kernel<<<(n + 255) / 256, 256, 0, static_cast<hipStream_t>(stream)>>>(p, n);
   return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// The graph of one batch, built node by node (no stream is put into capture
+// mode, so other threads' device-wide calls never meet a capturing stream):
+// the table copy from pinned host memory, the queue reset, the persistent fit,
+// the FP64 refit and the count reduction, in that order.
+extern "C" int lpa_k_batch_graph(hipGraph_t* out, void* d_table, const void* h_table, size_t copy_bytes,
+                                 const BatchHeader* d_hdr, const LaunchK* d_frames, const int64_t* d_first,
+                                 int32_t* d_queue, int32_t src_kind, int32_t block, int32_t lds_floats2,
+                                 int32_t grid, int32_t refit_grid, int32_t cap) {
+  *out = nullptr;
+  hipGraph_t g = nullptr;
+  if (hipGraphCreate(&g, 0) != hipSuccess) return -2;
+  hipGraphNode_t n_copy = nullptr, n_zero = nullptr, n_fit = nullptr, n_refit = nullptr, n_stats = nullptr;
+  hipError_t e = hipGraphAddMemcpyNode1D(&n_copy, g, nullptr, 0, d_table, h_table, copy_bytes, hipMemcpyHostToDevice);
+  hipKernelNodeParams p{};
+  int n_q = kXcds;
+  void* zero_args[] = {&d_queue, &n_q};
+  p.func = reinterpret_cast<void*>(&zero_i32_kernel);
+  p.gridDim = dim3(1);
+  p.blockDim = dim3(64);
+  p.sharedMemBytes = 0;
+  p.kernelParams = zero_args;
+  p.extra = nullptr;
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n_zero, g, &n_copy, 1, &p);
+  void* fit_args[] = {&d_hdr, &d_frames, &d_first, &d_queue};
+  switch (src_kind) {
+    case SRC_RAW_U16: p.func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_RAW_U16>); break;
+    case SRC_RAW_F32: p.func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_RAW_F32>); break;
+    case SRC_PLANE_F32: p.func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_PLANE_F32>); break;
+    case SRC_PLANE_F16: p.func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_PLANE_F16>); break;
+    default: e = hipErrorInvalidValue;
+  }
+  p.gridDim = dim3(grid);
+  p.blockDim = dim3(block);
+  p.sharedMemBytes = (unsigned)((size_t)lds_floats2 * sizeof(float2));
+  p.kernelParams = fit_args;
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n_fit, g, &n_zero, 1, &p);
+  void* refit_args[] = {&d_hdr, &d_frames, &d_first};
+  p.func = reinterpret_cast<void*>(&refit_batch_kernel);
+  p.gridDim = dim3(refit_grid);
+  p.blockDim = dim3(kRefitBlock);
+  p.sharedMemBytes = (unsigned)((size_t)lds_floats2 * 4);
+  p.kernelParams = refit_args;
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n_refit, g, &n_fit, 1, &p);
+  void* stats_args[] = {&d_hdr, &d_frames};
+  p.func = reinterpret_cast<void*>(&stats_frames_kernel);
+  p.gridDim = dim3(cap);
+  p.blockDim = dim3(256);
+  p.sharedMemBytes = 0;
+  p.kernelParams = stats_args;
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n_stats, g, &n_refit, 1, &p);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return -2;
+  }
+  *out = g;
+  return 0;
 }
