@@ -347,6 +347,22 @@ lpa_status lpa_autotune(lpa_rig* rig, const lpa_frame* frame, const lpa_params* 
 lpa_status lpa_tuner_save(lpa_ctx* ctx, const char* path);
 lpa_status lpa_tuner_load(lpa_ctx* ctx, const char* path);
 
+/* Kernel timing, a profiling aid.  While it is on, every lpa_reconstruct and
+ * lpa_reconstruct_plain on the context (not the allocation-free form) brackets
+ * its fit launch (isotropic, pre-computed-weight or, for CALPA, steered) and
+ * its FP64 refit launch with HIP events on the caller's stream.
+ * lpa_kernel_times waits for every bracketed launch recorded since timing was
+ * switched on or last read, returns the total milliseconds and launch counts
+ * of each kernel, and clears the records.  Switching it on or off clears
+ * them too.  Off by default: then no event is recorded.  The brackets include
+ * the gaps between back-to-back launches (a few microseconds). */
+typedef struct {
+  double fit_ms, refit_ms;     /* summed launch durations */
+  int64_t n_fit, n_refit;      /* bracketed launches */
+} lpa_kernel_time;
+lpa_status lpa_set_kernel_timing(lpa_ctx* ctx, int32_t on);
+lpa_status lpa_kernel_times(lpa_ctx* ctx, lpa_kernel_time* out);
+
 /* Thread-local message of the last non-OK status returned on this thread. */
 const char* lpa_last_error(void);
 

@@ -263,6 +263,18 @@ constexpr double kDefaultValueTol = 1e-4;
 // an FP32 emulation of the fit on the full workload's supports gave at most
 // 5.5 u times the componentwise condition, which S bounds from above.
 constexpr double kRoundingFactor = 8.0;
+// Window weights are computed from FP32 offsets, whose rounding moves |s d|^2
+// by up to about kOffsetRounding u |s d|^2 (the box origin, the steps and the
+// square each round once).  The weight then moves by ln2 2^-|s d|^2 times
+// that: relative to the weight this stays bounded inside the window but not
+// near its edge, where the weight vanishes while 2^-|s d|^2 tends to e_edge.
+// The part not proportional to the weight, up to ln2 e_edge R^2 iv per sample
+// (R^2 = |s r'|^2), enters the bound as edge_coef times
+// G_R (sum iv |f| + C_R sum iv) over the samples within reach, with G_R and
+// C_R the sums |g_i|, |C_i| times the monomials' bound on the window.  An FP32
+// emulation of the fits on 16x resampled output (few samples per window,
+// order 1), where this term decides, needed a multiple of 2.
+constexpr double kOffsetRounding = 4.0;
 
 // Fill the launch-dependent parts of a descriptor.  Returns false if the
 // LDS footprint of the requested tile does not fit.
@@ -317,6 +329,9 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_frame* 
       K->sc[m].reach2[cls] = (float)(reach * reach);
       K->sc[m].e_edge[cls] = (float)std::exp(-r * r / h);
       K->sc[m].h[cls] = h;
+      K->sc[m].edge_coef[cls] = (float)(kOffsetRounding * std::log(2.0) * std::exp(-r * r / h) * (cs * r) * (cs * r) /
+                                        kRoundingFactor);
+      K->sc[m].mono_r[cls] = (float)(cs * r * (1 + 1e-4));
     }
   }
   int lds = 0;
@@ -588,13 +603,62 @@ static lpa_status calpa_impl(lpa_rig* rig, const lpa_frame* frame, const Resolve
   size_t cbytes = 0, rbytes = 0;
   if (st == LPA_OK) st = stats_begin(ctx, out, &Ks, hs, &cbuf, &cbytes);
   if (st == LPA_OK) st = refit_begin(ctx, &Ks, hs, &rbuf, &rbytes);
+  KernelBracket kb(ctx, hs);
+  if (st == LPA_OK) kb.mark(0);
   if (st == LPA_OK && lpa_k_fit_steered(&Ks, hs) != 0) st = device_error(ctx, hipGetLastError(), "steered fit launch");
+  if (st == LPA_OK) kb.mark(1);
   st = refit_end(ctx, Ks, hs, rbuf, rbytes, st);
+  if (st == LPA_OK) {
+    if (rbuf) kb.mark(2);
+    kb.commit(rbuf != nullptr);
+  }
   st = stats_end(ctx, out, Ks, hs, cbuf, cbytes, st);
   for (int s = 0; s < rig->n; ++s) free_async(ctx, planes[s], plane_bytes[s], hs);
   free_async(ctx, gbuf, gbytes, hs);
   free_async(ctx, sbuf, sbytes, hs);
   return st;
+}
+
+KernelBracket::KernelBracket(lpa_ctx* ctx, hipStream_t hs) : ctx_(ctx), hs_(hs) {
+  {
+    std::lock_guard<std::mutex> g(ctx->timing_mu);
+    on_ = ctx->timing;
+  }
+  if (!on_) return;
+  for (auto& e : ev_)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      on_ = false;
+    }
+}
+
+KernelBracket::~KernelBracket() {
+  for (auto& e : ev_)
+    if (e) (void)hipEventDestroy(e);
+}
+
+void KernelBracket::mark(int i) {
+  if (on_ && hipEventRecord(ev_[i], hs_) != hipSuccess) on_ = false;
+}
+
+void KernelBracket::commit(bool refit_launched) {
+  if (!on_) return;
+  on_ = false;
+  if (!refit_launched) {
+    (void)hipEventDestroy(ev_[2]);
+    ev_[2] = nullptr;
+  }
+  std::lock_guard<std::mutex> g(ctx_->timing_mu);
+  if (!ctx_->timing) return;  // switched off meanwhile: the destructor frees the events
+  ctx_->timing_events.push_back(ev_);
+  ev_ = {};
+}
+
+void timing_clear_locked(lpa_ctx* ctx) {
+  for (auto& f : ctx->timing_events)
+    for (auto& e : f)
+      if (e) (void)hipEventDestroy(e);
+  ctx->timing_events.clear();
 }
 
 // Register budget of the pre-computed-weight kernel (waves per SIMD; 0 = 3).
@@ -672,9 +736,16 @@ lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_para
   size_t cbytes = 0, rbytes = 0;
   if (st == LPA_OK) st = stats_begin(ctx, out, &K, hs, &cbuf, &cbytes);
   if (st == LPA_OK) st = refit_begin(ctx, &K, hs, &rbuf, &rbytes);
+  KernelBracket kb(ctx, hs);
+  if (st == LPA_OK) kb.mark(0);
   if (st == LPA_OK && (stencil ? lpa_k_fit_stencil(&K, hs) : lpa_k_fit(&K, hs)) != 0)
     st = device_error(ctx, hipGetLastError(), "fit launch");
+  if (st == LPA_OK) kb.mark(1);
   st = refit_end(ctx, K, hs, rbuf, rbytes, st);
+  if (st == LPA_OK) {
+    if (rbuf) kb.mark(2);
+    kb.commit(rbuf != nullptr);
+  }
   st = stats_end(ctx, out, K, hs, cbuf, cbytes, st);
   for (int s = 0; s < rig->n; ++s) free_async(ctx, planes[s], plane_bytes[s], hs);
   return st;
@@ -687,6 +758,48 @@ using namespace lpa;
 extern "C" {
 
 const char* lpa_last_error(void) { return g_last_error; }
+
+lpa_status lpa_set_kernel_timing(lpa_ctx* ctx, int32_t on) {
+  lpa_status st = check_ctx(ctx);
+  if (st != LPA_OK) return st;
+  std::lock_guard<std::mutex> g(ctx->timing_mu);
+  timing_clear_locked(ctx);
+  ctx->timing = on != 0;
+  return LPA_OK;
+}
+
+lpa_status lpa_kernel_times(lpa_ctx* ctx, lpa_kernel_time* out) {
+  if (!out) return set_error(LPA_ERR_INVALID_ARG, "out is NULL");
+  lpa_status st = check_ctx(ctx);
+  if (st != LPA_OK) return st;
+  std::vector<std::array<hipEvent_t, 3>> evs;
+  {
+    std::lock_guard<std::mutex> g(ctx->timing_mu);
+    evs.swap(ctx->timing_events);
+  }
+  *out = lpa_kernel_time{};
+  hipError_t e = hipSetDevice(ctx->device);
+  for (auto& f : evs) {
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventSynchronize(f[2] ? f[2] : f[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, f[0], f[1]);
+    if (e == hipSuccess) {
+      out->fit_ms += ms;
+      out->n_fit += 1;
+    }
+    if (e == hipSuccess && f[2]) {
+      e = hipEventElapsedTime(&ms, f[1], f[2]);
+      if (e == hipSuccess) {
+        out->refit_ms += ms;
+        out->n_refit += 1;
+      }
+    }
+    for (auto& x : f)
+      if (x) (void)hipEventDestroy(x);
+  }
+  if (e != hipSuccess) return device_error(ctx, e, "kernel timing events");
+  return LPA_OK;
+}
 
 lpa_status lpa_create_ctx(int device, size_t hbm_budget_bytes, lpa_ctx** out) {
   if (!out) return set_error(LPA_ERR_INVALID_ARG, "out is NULL");
@@ -740,6 +853,10 @@ lpa_status lpa_destroy_ctx(lpa_ctx* ctx) {
     ctx->rigs.clear();
   }
   for (lpa_rig* r : rigs) rig_free(r);
+  {
+    std::lock_guard<std::mutex> g(ctx->timing_mu);
+    timing_clear_locked(ctx);
+  }
   (void)hipGetLastError();
   delete ctx;
   return LPA_OK;

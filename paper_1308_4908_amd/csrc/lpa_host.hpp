@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <atomic>
 #include <condition_variable>
 #include <cstdint>
@@ -136,6 +137,11 @@ struct lpa_ctx {
   // live rigs (destroyed with the context)
   std::mutex rigs_mu;
   std::set<lpa_rig*> rigs;
+  // kernel timing (lpa_set_kernel_timing): per bracketed frame, events before
+  // the fit, after the fit and after the refit (null: no refit launched)
+  std::mutex timing_mu;
+  bool timing = false;
+  std::vector<std::array<hipEvent_t, 3>> timing_events;
 };
 
 struct lpa_rig {
@@ -216,5 +222,24 @@ lpa_status check_batchable(const lpa_rig* rig, const Resolved& R, const lpa_fram
 lpa_status noalloc_init_device(int device);
 lpa_status serve_init(lpa_ctx* ctx);
 void serve_shutdown(lpa_ctx* ctx);
+
+// Kernel timing of one frame (lpa_set_kernel_timing): when the context's
+// timing is on, mark(0) before the fit launch, mark(1) after it, mark(2)
+// after the refit launch; commit() hands the events to the context.  Events
+// of a frame that is not committed (an error path) are destroyed.
+class KernelBracket {
+ public:
+  KernelBracket(lpa_ctx* ctx, hipStream_t hs);
+  ~KernelBracket();
+  void mark(int i);
+  void commit(bool refit_launched);
+
+ private:
+  lpa_ctx* ctx_;
+  hipStream_t hs_;
+  std::array<hipEvent_t, 3> ev_{};
+  bool on_ = false;
+};
+void timing_clear_locked(lpa_ctx* ctx);
 
 }  // namespace lpa

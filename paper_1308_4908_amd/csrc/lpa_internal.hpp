@@ -65,6 +65,15 @@ struct ScaleK {
   float reach2[2];    // (s r' (1 + 1e-4))^2: samples at or beyond it have exactly zero weight
   float e_edge[2];    // exp(-r'^2 / h'): subtracted so the window vanishes at r'
   double h[2];        // h' = h * kappa_class^2 (FP64 refit)
+  // Rounding bound of window weights from FP32 offsets: an offset's rounding
+  // moves |s d|^2 by up to a few u |s d|^2, the weight by ln2 2^-|s d|^2 times
+  // that, which the moment bound covers except for a part up to
+  // ln2 e_edge R^2 (R = s r') times iv per sample; edge_coef is that factor
+  // (with the offsets' rounding multiple, over the moment bound's), mono_r
+  // bounds |s dx|, |s dy| on the isotropic window (s r', a steered window
+  // scales it by its own extent).
+  float edge_coef[2];
+  float mono_r[2];
 };
 
 // Pre-computed window weights (rigs whose sensor maps and output map are

@@ -60,6 +60,9 @@ struct Acc {
   float b[n_basis<ORDER>()];          // sum w * f * phi
   float B[ICI ? n_mom<ORDER>() : 1];  // sum K w * monomial (variance of C0)
   float f2;                           // sum w f^2 (bounds the rounding error of C0)
+  // sum iv and sum iv |f| over the samples within reach (zero for tabulated
+  // windows): bound the error of window weights computed from FP32 offsets
+  float siv, sivf;
 };
 
 template <int ORDER, bool ICI>
@@ -71,6 +74,8 @@ __device__ __forceinline__ void acc_zero(Acc<ORDER, ICI>& a) {
 #pragma unroll
   for (int k = 0; k < (ICI ? n_mom<ORDER>() : 1); ++k) a.B[k] = 0.f;
   a.f2 = 0.f;
+  a.siv = 0.f;
+  a.sivf = 0.f;
 }
 
 // One sample: scaled offset (dx, dy), radiance f, inverse variance iv.  The
@@ -101,6 +106,8 @@ __device__ __forceinline__ bool acc_sample(Acc<ORDER, ICI>& a, float dx, float d
     // cut at zero (one instruction: the subtraction's clamp modifier).
     const float kw = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-r2) - e_edge, 0.f, 1.f);
     const float w = kw * iv;
+    a.siv += iv;
+    a.sivf = __builtin_fmaf(iv, fabsf(f), a.sivf);
     if constexpr (ORDER >= 2) {
       // Order 2: the weighted products w d^a for |a| <= 2 are the moments of
       // degree <= 2 and the basis terms of b; each moment of degree 3 and 4 is
@@ -203,9 +210,13 @@ __device__ __forceinline__ float rcp_t<float>(float x) { return __builtin_amdgcn
 template <>
 __device__ __forceinline__ double rcp_t<double>(double x) { return 1.0 / x; }
 
+// With BOUND, the top order's s also takes the window-weight term
+// edge.x * G_R * (sivf + C_R * siv), G_R = sum_i |g_i| mr^deg_i and C_R the
+// same of the coefficients, mr = edge.y bounding |dx|, |dy| on the window.
 template <typename T, int ORDER, bool ICI, bool BOUND = false>
 __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T tau, bool lower,
-                                           Fits<T, ORDER>& out, T f2 = T(0)) {
+                                           Fits<T, ORDER>& out, T f2 = T(0), T siv = T(0), T sivf = T(0),
+                                           float2 edge = float2{0.f, 0.f}) {
   constexpr int NB = n_basis<ORDER>();
   T L[NB][NB], U[NB][NB];  // U[i][k] = L[i][k] D[k]
   T D[NB], iD[NB], req[NB];
@@ -308,7 +319,8 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T
     // always recomputed in FP64)
     if constexpr (BOUND) if (o == ORDER) {
       T c[NB];
-      T sg = T(0), scs = T(0);
+      T sg = T(0), scs = T(0), gr = T(0), cr = T(0);
+      const T mr2 = edge.y * edge.y;
 #pragma unroll
       for (int i = NB - 1; i >= 0; --i) {
         if (i < no) {
@@ -319,11 +331,16 @@ __device__ __forceinline__ void solve_fits(const T* m, const T* b, const T* B, T
           c[i] = t;
           sg = __builtin_fmaf(fabsf(g[i]), sq[i], sg);
           scs = __builtin_fmaf(fabsf(t), sq[i], scs);
+          // bound of |monomial i| on the window: mr^deg (basis 0 | 1, 2 | 3, 4, 5)
+          const T mono = i == 0 ? T(1) : (i < 3 ? edge.y : mr2);
+          gr = __builtin_fmaf(fabsf(g[i]), mono, gr);
+          cr = __builtin_fmaf(fabsf(t), mono, cr);
         } else {
           c[i] = T(0);
         }
       }
-      out.s[o] = sg * (__builtin_amdgcn_sqrtf(fmaxf(f2, T(0))) + scs);
+      out.s[o] = __builtin_fmaf(edge.x * gr, __builtin_fmaf(cr, siv, sivf),
+                                sg * (__builtin_amdgcn_sqrtf(fmaxf(f2, T(0))) + scs));
     }
     out.rho[o] = (diag_all && rho > T(0)) ? rho : T(0);
     // Provisional: the caller also requires >= no samples where rho alone
@@ -1125,6 +1142,9 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
   const double Yj = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
   SteerC sc = {1.f, 1.f, 0.f};  // lanes outside the grid keep the isotropic window (inside the box)
   SteerBox sb = {0.f, 0.f, 0.f};
+  // the window's extent along x and y over its isotropic radius: on the
+  // ellipse d^T C d < r^2, |d_x| <= r sqrt((C^-1)_xx)
+  float stretch = 1.f;
   if constexpr (STEER) {
     float pxx = 0.f, pyy = 0.f, pxy = 0.f;  // C^-1 of the active lanes
     if (active) {
@@ -1135,6 +1155,7 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
       pxx = c.z * id;
       pyy = c.x * id;
       pxy = fabsf(c.y * id);
+      stretch = sqrtf(fmaxf(pxx, pyy));
     }
     sb = {wave_max(pxx), wave_max(pyy), wave_max(pxy)};
   }
@@ -1185,7 +1206,8 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
       // for fallback) are no longer solved.
       const bool lower = __builtin_amdgcn_ballot_w64(!st[ORDER].any) != 0;
       Fits<float, ORDER> fr;
-      solve_fits<float, ORDER, ICI, true>(a.m, a.b, a.B, K.tau_inv, lower, fr, a.f2);
+      solve_fits<float, ORDER, ICI, true>(a.m, a.b, a.B, K.tau_inv, lower, fr, a.f2, a.siv, a.sivf,
+                                          float2{K.sc[m].edge_coef[cls], K.sc[m].mono_r[cls] * stretch});
       // The top order's rounding risk, formed here: the empty asm keeps the
       // compiler from sinking the bound's arithmetic (and with it the factors
       // it reads) past the FP64 pass below.

@@ -95,6 +95,11 @@ class TuneResult(ctypes.Structure):
     ]
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("fit_ms", ctypes.c_double), ("refit_ms", ctypes.c_double), ("n_fit", ctypes.c_int64),
+                ("n_refit", ctypes.c_int64)]
+
+
 class Result(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("t_arrival_ns", ctypes.c_int64),
@@ -130,6 +135,8 @@ SIGNATURES = {
                                       ctypes.POINTER(TuneResult)]),
     "lpa_tuner_save": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_char_p]),
     "lpa_tuner_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_char_p]),
+    "lpa_set_kernel_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "lpa_kernel_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(KernelTime)]),
     "lpa_last_error": (ctypes.c_char_p, []),
 }
 
@@ -182,6 +189,8 @@ lpa_drain = _c("lpa_drain")
 lpa_autotune = _c("lpa_autotune")
 lpa_tuner_save = _c("lpa_tuner_save")
 lpa_tuner_load = _c("lpa_tuner_load")
+lpa_set_kernel_timing = _c("lpa_set_kernel_timing")
+lpa_kernel_times = _c("lpa_kernel_times")
 lpa_last_error = _c("lpa_last_error")
 
 
@@ -391,6 +400,14 @@ class Context:
 
     def drain(self):
         check(lpa_drain(self.handle))
+
+    def set_kernel_timing(self, on: bool):
+        check(lpa_set_kernel_timing(self.handle, 1 if on else 0))
+
+    def kernel_times(self) -> KernelTime:
+        t = KernelTime()
+        check(lpa_kernel_times(self.handle, ctypes.byref(t)))
+        return t
 
 
 class Rig:

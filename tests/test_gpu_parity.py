@@ -243,7 +243,7 @@ def test_resampled_output(torch_mod, ctx):
     raws = configs.capture_all(scene, sensors, 3000)
     _say("[gpu] resampled 4096^2 output")
     rgb, smap = run_gpu(torch_mod, ctx, sensors, raws, params)
-    pix = sample_pixels(4096, 4096, 1500, 78)
+    pix = sample_pixels(4096, 4096, 16384, 78)
     conv = [fp16_round_dn(r, s) for r, s in zip(raws, sensors)]
     orc = oracle.reconstruct([c[1] for c in conv], [c[0] for c in conv], params, pixels=pix, want_fits=True)
     st = compare(rgb[pix[:, 1], pix[:, 0]], smap[pix[:, 1], pix[:, 0]], orc, sensors, 1)
