@@ -72,6 +72,12 @@ MUTATIONS = [
      "const double rv = s->read_sigma * s->read_sigma;"),
     ("saturation frame ignored", "const double sat = pix && s->sat ? s->sat[i] : s->saturation;",
      "const double sat = s->saturation;"),
+    # rounding-sensitivity diagnostics
+    ("sens_y without the b terms", "    sy += fabs(g[i]) * ba[i];\n", "\n"),
+    ("sens_y without the A terms", "sy += fabs(g[i]) * Aa[i][j] * fabs(C[j]);", "sy += 0.0 * Aa[i][j];"),
+    ("sens_v without the factor 2", "sv += 2.0 * fabs(Bg[i])", "sv += fabs(Bg[i])"),
+    ("sens_v with signed A", "q += Aa[i][j] * fabs(g[j]);", "q += A[i][j] * g[j];"),
+    ("l1f without the window", "l1f += fabs(gp * s->k * s->ivar * s->f);", "l1f += fabs(gp * s->ivar * s->f);"),
     ("defect mask ignored", "if (pix && s->defect && s->defect[i]) return 0;", "if (0) return 0;"),
 ]
 

@@ -180,6 +180,95 @@ def test_bruteforce_lstsq(order):
 
 
 # --------------------------------------------------------------------------
+# Rounding-sensitivity diagnostics of a fit (Sec. 5.2, eq. (wlsqe) solved
+# from moment sums), pinned by experiment rather than by their formulas:
+#   l1f    = sum_k |a_k f_k| with a = e0^T pinv(sqrt(W) Phi) sqrt(W), the
+#            equivalent-kernel weights from numpy's pseudo-inverse;
+#   sens_y = the first-order change of C0 when every term of every moment sum
+#            of A and b moves by a relative eps with the worst signs: the
+#            perturbed systems are re-solved with numpy (central difference),
+#            and random sign patterns must stay within eps sens_y;
+#   sens_v = an upper bound of the same experiment on the variance g^T B g
+#            (terms of A and B perturbed), attained for order 0.
+# --------------------------------------------------------------------------
+def _perturbed_terms(S, n):
+    dx, dy, fh, var, k = S.T
+    Phi = np.stack([np.ones_like(dx), dx, dy, dx * dx, dx * dy, dy * dy], 1)[:, :n]
+    w = k / var
+    tA = w[:, None, None] * Phi[:, :, None] * Phi[:, None, :]      # terms of A (k, i, j)
+    tB = (k * k / var)[:, None, None] * Phi[:, :, None] * Phi[:, None, :]
+    tb = (w * fh)[:, None] * Phi                                   # terms of b (k, i)
+    return Phi, w, fh, tA, tB, tb
+
+
+def _c0(tA, tb, dA, db):
+    A = np.sum(tA * (1 + dA), 0)
+    b = np.sum(tb * (1 + db), 0)
+    return np.linalg.solve(A, b)[0]
+
+
+def _var(tA, tB, dA, dB):
+    A = np.sum(tA * (1 + dA), 0)
+    B = np.sum(tB * (1 + dB), 0)
+    g = np.linalg.solve(A, np.eye(A.shape[0])[0])
+    return g @ B @ g
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_rounding_sensitivities(order):
+    rng = np.random.default_rng(71 + order)
+    size = 12
+    sensors = [_sensor(size, size, _affine(rng, 0.0, 1.0, 1.0), e, saturation=4095.0) for e in (1.0, 1 / 8)]
+    from synth.scene import EdgeScene
+    scene = EdgeScene(size, size, 9 + order, n_lines=3)
+    raws = [R.capture(scene, s, (77, i)) for i, s in enumerate(sensors)]
+    radii = [2.0, 3.0]
+    params = _params(size, size, order, radii)
+    pix = np.array([[4, 5], [6, 6], [7, 4], [5, 7]], np.int32)
+    res = oracle.reconstruct(sensors, raws, params, pixels=pix, want_fits=True)
+    n = {0: 1, 1: 3, 2: 6}[order]
+    eps = 1e-6
+    checked = 0
+    for p, (u, v) in enumerate(pix):
+        for c in range(3):
+            for m, r in enumerate(radii):
+                fit = res["fits"][p, c, m, order]
+                if not fit["valid"] or fit["rho"] < 1e-3:
+                    continue
+                S = _support(sensors, raws, float(u), float(v), c, r, 2 * r * r / 9)
+                Phi, w, fh, tA, tB, tb = _perturbed_terms(S, n)
+                sw = np.sqrt(w)
+                a = np.linalg.pinv(Phi * sw[:, None])[0] * sw
+                assert fit["l1f"] == pytest.approx(np.sum(np.abs(a * fh)), rel=1e-8)
+                A = np.sum(tA, 0)
+                g = np.linalg.solve(A, np.eye(n)[0])
+                C = np.linalg.solve(A, np.sum(tb, 0))
+                # C0: worst signs raise C0 by eps sens_y to first order
+                db = np.sign(g[None, :] * tb)
+                dA = -np.sign(g[None, :, None] * tA * C[None, None, :])
+                slope = (_c0(tA, tb, eps * dA, eps * db) - _c0(tA, tb, -eps * dA, -eps * db)) / (2 * eps)
+                assert slope == pytest.approx(fit["sens_y"], rel=1e-5)
+                for _ in range(8):
+                    rA = rng.choice([-1.0, 1.0], tA.shape)
+                    rb = rng.choice([-1.0, 1.0], tb.shape)
+                    dev = abs(_c0(tA, tb, eps * rA, eps * rb) - fit["yhat"]) / eps
+                    assert dev <= fit["sens_y"] * (1 + 1e-4) + 1e-9 * abs(fit["yhat"]) / eps
+                # variance: the worst signs of the exact first-order change
+                Bm = np.sum(tB, 0)
+                h = np.linalg.solve(A.T, Bm @ g)
+                dB = np.sign(g[None, :, None] * tB * g[None, None, :])
+                dA = -np.sign(h[None, :, None] * tA * g[None, None, :])
+                slope_v = (_var(tA, tB, eps * dA, eps * dB) - _var(tA, tB, -eps * dA, -eps * dB)) / (2 * eps)
+                assert slope_v <= fit["sens_v"] * (1 + 1e-5)
+                if order == 0:
+                    assert slope_v == pytest.approx(fit["sens_v"], rel=1e-5)
+                else:
+                    assert slope_v >= 0.05 * fit["sens_v"]
+                checked += 1
+    assert checked >= 8
+
+
+# --------------------------------------------------------------------------
 # Bilinear demosaicing special case: one aligned sensor, identity output,
 # M = 0, r = 1.5 for R/B and r_G = 1.2 (kappa_G = 0.8), equal noise variances.
 # The supports are then exactly the bilinear-interpolation neighbourhoods
