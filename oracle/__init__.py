@@ -154,6 +154,12 @@ def _load():
             ctypes.POINTER(_Params), ctypes.POINTER(_Adapt), ctypes.c_void_p, ctypes.c_void_p,
             ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
         ]
+        lib.orc_reconstruct_temporal.restype = ctypes.c_int
+        lib.orc_reconstruct_temporal.argtypes = [
+            ctypes.POINTER(_Sensor), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+            ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_int64,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ]
         lib.orc_sample_radiance.restype = ctypes.c_int
         lib.orc_sample_radiance.argtypes = [
             ctypes.POINTER(_Sensor), ctypes.c_double, ctypes.POINTER(ctypes.c_double),
@@ -260,6 +266,55 @@ def reconstruct(sensors, raws, params, pixels=None, want_fits=False, exhaustive=
     rc = lib.orc_reconstruct(
         sens, ns, ptrs, ctypes.byref(prm), pix_ptr, n, rgb.ctypes.data, smap.ctypes.data,
         margin.ctypes.data, gap.ctypes.data, fits.ctypes.data if fits is not None else None,
+    )
+    if rc != 0:
+        raise ValueError(f"oracle rejected its arguments (code {rc})")
+    out = {"rgb": rgb, "scale_map": smap, "margin": margin, "gap": gap}
+    if fits is not None:
+        out["fits"] = fits
+    return out
+
+
+def reconstruct_temporal(sensors, frames, params, pixels=None, want_fits=False, exhaustive=False):
+    """Temporal LPA (readings T1-T4 in lpa_oracle.h): frames[t] is the list of
+    the sensors' raw planes at time -t (frames[0] the output's frame);
+    params["h_t"] gives one temporal scale per radius (0: only t = 0).
+    Returns the same dict as reconstruct()."""
+    lib = _load()
+    ns = len(sensors)
+    nt = len(frames)
+    structs = [_sensor_struct(d) for d in sensors]
+    sens = (_Sensor * ns)(*structs)
+    planes = []
+    for fr in frames:
+        if len(fr) != ns:
+            raise ValueError("every frame holds one raw plane per sensor")
+        for d, r in zip(sensors, fr):
+            pl = np.ascontiguousarray(np.asarray(r), dtype=np.float64)
+            if pl.shape != (int(d["height"]), int(d["width"])):
+                raise ValueError(f"raw plane shape {pl.shape} does not match sensor {d['height']}x{d['width']}")
+            planes.append(pl)
+    ptrs = (ctypes.c_void_p * (ns * nt))(*[pl.ctypes.data for pl in planes])
+    prm = _params_struct(params, exhaustive)
+    ht = np.ascontiguousarray(np.asarray(params["h_t"], dtype=np.float64).reshape(-1))
+    if ht.size != prm.n_scales:
+        raise ValueError("h_t needs one temporal scale per radius")
+    if pixels is None:
+        n = prm.out_w * prm.out_h
+        pix_ptr = None
+    else:
+        pix = np.ascontiguousarray(np.asarray(pixels, dtype=np.int32).reshape(-1, 2))
+        n = pix.shape[0]
+        pix_ptr = pix.ctypes.data
+    rgb = np.empty((n, 3), np.float64)
+    smap = np.empty((n, 3), np.uint8)
+    margin = np.empty((n, 3), np.float64)
+    gap = np.empty((n, 3), np.float64)
+    fits = np.zeros((n, 3, prm.n_scales, 3), FIT_DTYPE) if want_fits else None
+    rc = lib.orc_reconstruct_temporal(
+        sens, ns, nt, ptrs, ctypes.byref(prm), ht.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), pix_ptr, n,
+        rgb.ctypes.data, smap.ctypes.data, margin.ctypes.data, gap.ctypes.data,
+        fits.ctypes.data if fits is not None else None,
     )
     if rc != 0:
         raise ValueError(f"oracle rejected its arguments (code {rc})")

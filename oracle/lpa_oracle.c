@@ -120,15 +120,11 @@ static void affine_apply(const double a[6], double x, double y, double* X, doubl
   *Y = a[3] * x + a[4] * y + a[5];
 }
 
-/* Support set of output position (X, Y) for channel c and radius r with
- * window parameter h (Sec. 5.2 supp W_H; Sec. 4.2 X = T_s(x); R2, R4, R5).
- * With a steering matrix C (3 entries, Sec. 5.4, R18) the window is
- * exp(-d'Cd / h) - exp(-r^2 / h) on the ellipse d'Cd < r^2; C == NULL is
- * the isotropic window (C = I). */
-static int gather_support(const orc_sensor* sensors, int n_sensors, const double* const* raw,
-                          double X, double Y, int c, double r, double h, const double* C,
-                          int exhaustive, sample_list* out) {
-  out->n = 0;
+/* The samples of one frame (all sensors) in the window of (X, Y), channel c,
+ * radius r, each window value times the frame's temporal factor kt; appended
+ * to out. */
+static int gather_frame(const orc_sensor* sensors, int n_sensors, const double* const* raw, double X, double Y,
+                        int c, double r, double h, const double* C, int exhaustive, double kt, sample_list* out) {
   const double k_edge = exp(-r * r / h);
   /* the ellipse lies inside the disc of radius r / sqrt(smallest eigenvalue of C) */
   double reff = r;
@@ -167,12 +163,32 @@ static int gather_support(const orc_sensor* sensors, int n_sensors, const double
         const double dx = Xk - X, dy = Yk - Y;
         const double d2 = C ? C[0] * dx * dx + 2.0 * C[1] * dx * dy + C[2] * dy * dy : dx * dx + dy * dy;
         if (!(d2 < r * r)) continue;
-        const double k = exp(-d2 / h) - k_edge;
+        const double k = (exp(-d2 / h) - k_edge) * kt;
         if (!(k > 0.0)) continue;
         orc_sample smp = {dx, dy, f, 1.0 / var, k};
         if (list_push(out, smp)) return -1;
       }
     }
+  }
+  return 0;
+}
+
+/* Support set of output position (X, Y) for channel c and radius r with
+ * window parameter h (Sec. 5.2 supp W_H; Sec. 4.2 X = T_s(x); R2, R4, R5).
+ * With a steering matrix C (3 entries, Sec. 5.4, R18) the window is
+ * exp(-d'Cd / h) - exp(-r^2 / h) on the ellipse d'Cd < r^2; C == NULL is
+ * the isotropic window (C = I).  Over n_times frames (raw[t * n_sensors + s]
+ * is sensor s at time -t) the window of a sample at time -t is multiplied by
+ * exp(-t^2 / h_t) (T2); with h_t = 0 only t = 0 belongs to the support. */
+static int gather_support(const orc_sensor* sensors, int n_sensors, const double* const* raw,
+                          double X, double Y, int c, double r, double h, const double* C,
+                          int exhaustive, int n_times, double h_t, sample_list* out) {
+  out->n = 0;
+  for (int t = 0; t < n_times; ++t) {
+    const double kt = t == 0 ? 1.0 : (h_t > 0.0 ? exp(-(double)t * t / h_t) : 0.0);
+    if (!(kt > 0.0)) continue;
+    if (gather_frame(sensors, n_sensors, raw + (size_t)t * n_sensors, X, Y, c, r, h, C, exhaustive, kt, out))
+      return -1;
   }
   return 0;
 }
@@ -353,27 +369,44 @@ static int check_args(const orc_sensor* sensors, int32_t n_sensors, const double
 }
 
 static int reconstruct_impl(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
-                            const orc_params* P, const double* Cpix, const int32_t* pixels,
-                            int64_t n_pixels, double* rgb, uint8_t* scale_map, double* margin,
-                            double* gap, orc_fit* fits);
+                            int32_t n_times, const double* h_t, const orc_params* P, const double* Cpix,
+                            const int32_t* pixels, int64_t n_pixels, double* rgb, uint8_t* scale_map,
+                            double* margin, double* gap, orc_fit* fits);
 
 int orc_reconstruct(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
                     const orc_params* P, const int32_t* pixels, int64_t n_pixels, double* rgb,
                     uint8_t* scale_map, double* margin, double* gap, orc_fit* fits) {
-  return reconstruct_impl(sensors, n_sensors, raw, P, NULL, pixels, n_pixels, rgb, scale_map, margin, gap, fits);
+  return reconstruct_impl(sensors, n_sensors, raw, 1, NULL, P, NULL, pixels, n_pixels, rgb, scale_map, margin, gap,
+                          fits);
 }
 
 int orc_reconstruct_steered(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
                             const orc_params* P, const double* C, const int32_t* pixels,
                             int64_t n_pixels, double* rgb, uint8_t* scale_map, double* margin,
                             double* gap, orc_fit* fits) {
-  return reconstruct_impl(sensors, n_sensors, raw, P, C, pixels, n_pixels, rgb, scale_map, margin, gap, fits);
+  return reconstruct_impl(sensors, n_sensors, raw, 1, NULL, P, C, pixels, n_pixels, rgb, scale_map, margin, gap,
+                          fits);
+}
+
+int orc_reconstruct_temporal(const orc_sensor* sensors, int32_t n_sensors, int32_t n_times,
+                             const double* const* raw, const orc_params* P, const double* h_t,
+                             const int32_t* pixels, int64_t n_pixels, double* rgb, uint8_t* scale_map,
+                             double* margin, double* gap, orc_fit* fits) {
+  if (n_times < 1 || n_times > ORC_MAX_TIMES || !h_t) return -8;
+  for (int m = 0; m < P->n_scales; ++m)
+    if (!(h_t[m] >= 0.0)) return -8;
+  for (int t = 1; t < n_times; ++t) {
+    const int rc = check_args(sensors, n_sensors, raw + (size_t)t * n_sensors, P, pixels, n_pixels);
+    if (rc) return rc;
+  }
+  return reconstruct_impl(sensors, n_sensors, raw, n_times, h_t, P, NULL, pixels, n_pixels, rgb, scale_map, margin,
+                          gap, fits);
 }
 
 static int reconstruct_impl(const orc_sensor* sensors, int32_t n_sensors, const double* const* raw,
-                            const orc_params* P, const double* Cpix, const int32_t* pixels,
-                            int64_t n_pixels, double* rgb, uint8_t* scale_map, double* margin,
-                            double* gap, orc_fit* fits) {
+                            int32_t n_times, const double* h_t, const orc_params* P, const double* Cpix,
+                            const int32_t* pixels, int64_t n_pixels, double* rgb, uint8_t* scale_map,
+                            double* margin, double* gap, orc_fit* fits) {
   const int rc = check_args(sensors, n_sensors, raw, P, pixels, n_pixels);
   if (rc) return rc;
   if (!rgb) return -1;
@@ -396,7 +429,7 @@ static int reconstruct_impl(const orc_sensor* sensors, int32_t n_sensors, const 
         const double h0 = P->h[m] > 0.0 ? P->h[m] : 2.0 * P->radii[m] * P->radii[m] / 9.0;
         const double h = h0 * kappa * kappa;
         if (gather_support(sensors, n_sensors, raw, X, Y, c, r, h, Cpix ? Cpix + 3 * p : NULL, P->exhaustive,
-                           &list)) {
+                           n_times, h_t ? h_t[m] : 0.0, &list)) {
           free(list.v);
           return -7;
         }
@@ -459,7 +492,7 @@ int orc_gradients(const orc_sensor* sensors, int32_t n_sensors, const double* co
     const int32_t v = pixels ? pixels[2 * p + 1] : (int32_t)(p / P->out_w);
     double X, Y;
     affine_apply(P->out_affine, (double)u, (double)v, &X, &Y);
-    if (gather_support(sensors, n_sensors, raw, X, Y, 1, r, h, NULL, P->exhaustive, &list)) {
+    if (gather_support(sensors, n_sensors, raw, X, Y, 1, r, h, NULL, P->exhaustive, 1, 0.0, &list)) {
       free(list.v);
       return -7;
     }

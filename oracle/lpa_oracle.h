@@ -211,6 +211,26 @@ int orc_reconstruct_steered(const orc_sensor* sensors, int32_t n_sensors, const 
                             int64_t n_pixels, double* rgb, uint8_t* scale_map, double* margin,
                             double* gap, orc_fit* fits);
 
+/* Temporal (3-D) LPA (Sec. 9 names the extension of the supports from space to
+ * space and time as future work; its form here is a reading of our own):
+ *   T1 n_times frames of the rig at integer times t = 0, -1, ..., -(n_times - 1)
+ *      (causal: the output is the estimate at t = 0); raw[t * n_sensors + s]
+ *      is sensor s's frame at time -t, all through the same sensor maps and
+ *      noise model;
+ *   T2 the window of a sample at time -t is the spatial window (R3) times
+ *      exp(-t^2 / h_t[m]), one temporal scale per radius, so that ICI selects
+ *      a spatio-temporal scale; h_t[m] = 0 keeps only t = 0;
+ *   T3 the local model is constant in t (the basis is the spatial one): the
+ *      support, not the polynomial, extends to time;
+ *   T4 no motion compensation: a scene that moves is handled by the scale
+ *      selection, which shrinks the support where frames disagree.
+ * Outputs as orc_reconstruct. */
+#define ORC_MAX_TIMES 16
+int orc_reconstruct_temporal(const orc_sensor* sensors, int32_t n_sensors, int32_t n_times,
+                             const double* const* raw, const orc_params* params, const double* h_t,
+                             const int32_t* pixels, int64_t n_pixels, double* rgb, uint8_t* scale_map,
+                             double* margin, double* gap, orc_fit* fits);
+
 #ifdef __cplusplus
 }
 #endif

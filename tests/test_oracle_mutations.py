@@ -18,8 +18,9 @@ SRC = os.path.join(ROOT, "oracle", "lpa_oracle.c")
 
 # (name, original text, planted mistake)
 MUTATIONS = [
-    ("window not truncated", "const double k = exp(-d2 / h) - k_edge;", "const double k = exp(-d2 / h);"),
-    ("window exp(-d2/h^2)", "const double k = exp(-d2 / h) - k_edge;", "const double k = exp(-d2 / (h * h)) - exp(-r * r / (h * h));"),
+    ("window not truncated", "const double k = (exp(-d2 / h) - k_edge) * kt;", "const double k = exp(-d2 / h) * kt;"),
+    ("window exp(-d2/h^2)", "const double k = (exp(-d2 / h) - k_edge) * kt;",
+     "const double k = (exp(-d2 / (h * h)) - exp(-r * r / (h * h))) * kt;"),
     ("weight 1/sigma", "orc_sample smp = {dx, dy, f, 1.0 / var, k};", "orc_sample smp = {dx, dy, f, 1.0 / sqrt(var), k};"),
     ("B without K^2", "const double w2 = s->k * s->k * s->ivar;", "const double w2 = s->k * s->ivar;"),
     ("basis dx*dy -> dx*dx", "phi[4] = dx * dy;", "phi[4] = dx * dx;"),
@@ -58,8 +59,8 @@ MUTATIONS = [
     ("analysis window short by a row", "for (int b = -q; b <= q; ++b) {", "for (int b = -q + 1; b <= q; ++b) {"),
     ("steering eigenvalue not clamped", "la = la < lo ? lo : (la > hi ? hi : la);", "la = la * 1.0;"),
     ("gradients of the R channel",
-     "gather_support(sensors, n_sensors, raw, X, Y, 1, r, h, NULL, P->exhaustive, &list)",
-     "gather_support(sensors, n_sensors, raw, X, Y, 0, r, h, NULL, P->exhaustive, &list)"),
+     "gather_support(sensors, n_sensors, raw, X, Y, 1, r, h, NULL, P->exhaustive, 1, 0.0, &list)",
+     "gather_support(sensors, n_sensors, raw, X, Y, 0, r, h, NULL, P->exhaustive, 1, 0.0, &list)"),
     ("ellipse box not widened", "reff = r / sqrt(lmin);", "reff = r;"),
     # per-pixel calibration frames (Sec. 6)
     ("non-uniformity not in the radiance", "const double f = (y - b) / (g * e * a);",
@@ -72,6 +73,13 @@ MUTATIONS = [
      "const double rv = s->read_sigma * s->read_sigma;"),
     ("saturation frame ignored", "const double sat = pix && s->sat ? s->sat[i] : s->saturation;",
      "const double sat = s->saturation;"),
+    # temporal LPA (T1-T4)
+    ("temporal weight one frame late", "exp(-(double)t * t / h_t)", "exp(-(double)(t + 1) * (t + 1) / h_t)"),
+    ("temporal weight outside the truncation", "const double k = (exp(-d2 / h) - k_edge) * kt;",
+     "const double k = exp(-d2 / h) * kt - k_edge;"),
+    ("frames indexed sensor-major", "raw + (size_t)t * n_sensors, X, Y", "raw + (size_t)t, X, Y"),
+    ("zero temporal scale keeps every frame", "(h_t > 0.0 ? exp(-(double)t * t / h_t) : 0.0)",
+     "(h_t > 0.0 ? exp(-(double)t * t / h_t) : 1.0)"),
     # rounding-sensitivity diagnostics
     ("sens_y without the b terms", "    sy += fabs(g[i]) * ba[i];\n", "\n"),
     ("sens_y without the A terms", "sy += fabs(g[i]) * Aa[i][j] * fabs(C[j]);", "sy += 0.0 * Aa[i][j];"),
@@ -101,6 +109,7 @@ def test_pins_catch_planted_mistake(name, orig, bad):
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                             os.path.join(ROOT, "tests", "test_oracle_calpa.py"),
-                            os.path.join(ROOT, "tests", "test_oracle_calib.py")],
+                            os.path.join(ROOT, "tests", "test_oracle_calib.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_temporal.py")],
                            cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake '{name}' passed every pin:\n{r.stdout[-2000:]}"
