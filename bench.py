@@ -17,7 +17,7 @@ launch stream); the FP64 oracle on a bounded band of the same frame on the
 host cores (one core, and every core of the process's share).  More legs:
 the small frame (3 x 256^2, order 1, one radius), the FP16-storage resample
 of the small rig to 4096^2, CALPA, calibration frames, pre-computed weights
-on a registered rig, a batch of 64 mixed frames in one persistent graph
+on a registered rig, temporal LPA over the current and previous frame, a batch of 64 mixed frames in one persistent graph
 launch (checked bit-for-bit against the same frames one plain launch each),
 and a served run of 8 cameras with Poisson arrivals at 30 fps each (60 s by
 default) reporting p50 / p99 frame latency.  Batched and served frames are
@@ -162,9 +162,10 @@ def gather(torch, t, pix):
 class Check:
     """Sampled GPU outputs of one leg, checked against the oracle in the oracle leg."""
 
-    def __init__(self, leg: dict, sensors, raws, params, pix, rgb, smap, steer=None):
+    def __init__(self, leg: dict, sensors, raws, params, pix, rgb, smap, steer=None, frames=None):
         self.leg, self.sensors, self.raws, self.params = leg, sensors, raws, params
         self.pix, self.rgb, self.smap, self.steer = pix, rgb, smap, steer
+        self.frames = frames  # temporal legs: the raw planes of every frame (frames[0] is raws)
 
 
 def frame_counts(stats, n_px: int) -> dict:
@@ -339,7 +340,7 @@ def serve_leg(torch, ctx, Rig, sensors, raws, configs, seconds, checks=None, n_c
 # Oracle leg: the CPU baseline, and the accuracy of every leg's samples.
 # ---------------------------------------------------------------------------
 
-def run_oracle(oracle, sensors, raws64, params, pix, threads, want_fits=False, steer=None):
+def run_oracle(oracle, sensors, raws64, params, pix, threads, want_fits=False, steer=None, frames64=None):
     """The oracle on the listed pixels, chunks spread over host threads (the
     oracle is reentrant and the C call releases the interpreter lock)."""
     from concurrent.futures import ThreadPoolExecutor
@@ -350,6 +351,8 @@ def run_oracle(oracle, sensors, raws64, params, pix, threads, want_fits=False, s
     chunks = np.array_split(np.arange(len(pix)), n_chunks)
 
     def one(ix):
+        if frames64 is not None:
+            return oracle.reconstruct_temporal(sensors, frames64, params, pixels=pix[ix], want_fits=want_fits)
         if steer is not None:
             return oracle.reconstruct_steered(sensors, raws64, params, steer[ix], pixels=pix[ix], want_fits=want_fits)
         return oracle.reconstruct(sensors, raws64, params, pixels=pix[ix], want_fits=want_fits)
@@ -443,7 +446,11 @@ def oracle_leg(sensors, raws, params, rows: int, checks, threads: int, avail: in
     by_leg = {}
     for ck in checks:
         r64 = [np.ascontiguousarray(r, dtype=np.float64) for r in ck.raws]
-        orc = run_oracle(oracle, ck.sensors, r64, ck.params, ck.pix, threads, want_fits=True, steer=ck.steer)
+        f64 = None
+        if ck.frames is not None:
+            f64 = [r64] + [[np.ascontiguousarray(r, dtype=np.float64) for r in fr] for fr in ck.frames[1:]]
+        orc = run_oracle(oracle, ck.sensors, r64, ck.params, ck.pix, threads, want_fits=True, steer=ck.steer,
+                         frames64=f64)
         by_leg.setdefault(id(ck.leg), (ck.leg, []))[1].append((orc, ck))
     for leg, items in by_leg.values():
         # pool the leg's samples (several frames for batched and served legs)
@@ -474,6 +481,7 @@ def main():
     ap.add_argument("--no-calib", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-resample", action="store_true")
+    ap.add_argument("--no-temporal", action="store_true")
     ap.add_argument("--batch-frames", type=int, default=64)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -707,6 +715,51 @@ def main():
         checks.append(Check(pre, a_sensors, a_raws, sp, pix, gather(torch, out, pix), gather(torch, smap, pix)))
         a_rig.close()
         del a_dev
+    temporal = None
+    if not args.no_temporal:
+        # temporal LPA over the current and the previous frame of the same
+        # static scene (new noise): 4 sensors x 2 frames = 8 staged sensors,
+        # one temporal scale per radius
+        say("generating the previous frame for the temporal leg")
+        prev = configs.capture_all(scene, sensors, 2001)
+        t_dev = [dev, [torch.from_numpy(r).cuda() for r in prev]]
+        tp = dict(params, h_t=[0.5, 1.0, 2.0, 4.0])
+        say("timing temporal LPA (4 sensors x 2 frames)")
+        for _ in range(2):
+            rig.reconstruct_temporal(t_dev, tp, out)
+        torch.cuda.synchronize()
+        n_t = max(3, args.steps // 2)
+        ctx.set_kernel_timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n_t):
+            rig.reconstruct_temporal(t_dev, tp, out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kt_t = ctx.kernel_times()
+        ctx.set_kernel_timing(False)
+        ms_t = e0.elapsed_time(e1) / n_t
+        t_flops, t_flop_px, _, t_updates = algorithmic_flops(raws + prev, sensors + sensors, n_px)
+        t_flops += t_updates * n_px  # the temporal factor: one product per update
+        t_ms_k = kt_t.fit_ms / max(kt_t.n_fit, 1)
+        t_ach = t_flops / (t_ms_k * 1e-3) / 1e12
+        temporal = {"workload": f"the headline rig over 2 frames (current + previous, same static scene, new noise): "
+                                f"4 sensors x 2 x {size}x{size} raw uint16, h_t = 0.5/1/2/4 frames^2 per radius",
+                    "value": round(n_px / (ms_t * 1e-3) / 1e6, 3), "unit": "Mpixel/s", "ms_per_frame": round(ms_t, 4),
+                    "vs_single_frame": round(ms_t / ms, 3),
+                    "form": "fit_kernel_temporal (every frame's sensors staged as sensors of their own) + FP64 refit",
+                    "roofline": {"bound": "alu", "achieved": round(t_ach, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": round(t_ach / PEAK_FP32_VECTOR_TFLOPS, 4),
+                                 "flop_per_pixel": round(t_flops / n_px, 1), "kernel_ms_per_launch": round(t_ms_k, 4)},
+                    "accuracy": None}
+        st = torch.zeros(2, dtype=torch.int64, device="cuda")
+        rig.reconstruct_temporal(t_dev, tp, out, smap, stats=st)
+        torch.cuda.synchronize()
+        temporal.update(frame_counts(st, n_px))
+        pix = sample_pixels(params["out_w"], params["out_h"], 4096, 2500)
+        checks.append(Check(temporal, sensors, raws, tp, pix, gather(torch, out, pix), gather(torch, smap, pix),
+                            frames=[raws, prev]))
+        del t_dev
     fit_ms = kt.fit_ms / max(kt.n_fit, 1)
     refit_ms = kt.refit_ms / max(kt.n_refit, 1) if kt.n_refit else 0.0
     achieved = flops / (fit_ms * 1e-3) / 1e12
@@ -755,6 +808,7 @@ def main():
         "calpa": calpa,
         "precomputed_weights": pre,
         "calibration_frames": calib,
+        "temporal": temporal,
         "speedup_vs_plain": round(value / plain["value"], 3) if plain else None,
         "roofline": roof,
         "refit": refit,

@@ -191,13 +191,19 @@ typedef struct {
    * are accumulated in FP32; with every fit the kernel computes a bound S on
    * how far the rounding of its moment terms can move C0 (per unit relative
    * rounding; an upper estimate of the componentwise condition of C0 in the
-   * moment terms), and where 8 * 2^-24 * S exceeds value_tol times the scale
-   * above, the chosen fit of that output is recomputed from FP64 products
-   * and sums of the same samples.  In HDR windows C0 is often a small
-   * difference of large terms, so a few percent of the outputs of the
-   * benchmark frame take this path.  0 selects 1e-4; a negative value never
-   * recomputes. */
+   * moment terms, plus a term for window weights computed from FP32 offsets),
+   * and where 8 * 2^-24 * S exceeds value_tol times the scale above, the
+   * chosen fit of that output is recomputed in FP64 from the raw frame (the
+   * decode, the sample positions, the window and the sums all in FP64).  In
+   * HDR windows C0 is often a small difference of large terms, so a few
+   * percent of the outputs of the benchmark frame take this path.  0 selects
+   * 1e-4; a negative value never recomputes. */
   double value_tol;
+  /* Temporal scale per radius, in frames^2 (lpa_reconstruct_temporal only):
+   * a sample of the frame at time -t has its window multiplied by
+   * exp(-t^2 / h_t[m]) at radius m; 0 keeps only the output's frame.  Else
+   * at least (n_times - 1)^2 / 16 (the oldest frame's factor >= e^-16). */
+  double h_t[LPA_MAX_SCALES];
 } lpa_params;
 
 enum { LPA_MODE_LPA = 0, LPA_MODE_CALPA = 1 };
@@ -346,6 +352,21 @@ lpa_status lpa_autotune(lpa_rig* rig, const lpa_frame* frame, const lpa_params* 
 /* Persist / restore the context's tuning choices (small JSON file). */
 lpa_status lpa_tuner_save(lpa_ctx* ctx, const char* path);
 lpa_status lpa_tuner_load(lpa_ctx* ctx, const char* path);
+
+/* Temporal LPA (Sec. 9 names the extension of the supports from space to
+ * space and time as future work; this form is a reading of it): frames[t]
+ * (t = 0 .. n_times - 1) is the rig's capture at time -t, frames[0] the frame
+ * reconstructed.  Every sample's window is the spatial one times
+ * exp(-t^2 / params->h_t[m]) for radius m, so ICI selects a spatio-temporal
+ * scale and shrinks the support where the frames disagree (no motion
+ * compensation); the local model is constant in t.  Mode LPA, isotropic
+ * windows, storage FUSED (raw frames read by the fit kernel), device frames
+ * of one dtype; n_times * n_sensors <= LPA_MAX_SENSORS (the kernel stages
+ * each frame's sensors as sensors of their own).  Outputs, validation and
+ * errors as lpa_reconstruct; LPA_ERR_UNSUPPORTED for other modes, storage
+ * forms and flags. */
+lpa_status lpa_reconstruct_temporal(lpa_rig* rig, const lpa_frame* frames, int32_t n_times,
+                                    const lpa_params* params, const lpa_output* out, void* hip_stream);
 
 /* Kernel timing, a profiling aid.  While it is on, every lpa_reconstruct and
  * lpa_reconstruct_plain on the context (not the allocation-free form) brackets

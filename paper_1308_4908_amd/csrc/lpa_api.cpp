@@ -751,11 +751,102 @@ lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_para
   return st;
 }
 
+// Temporal LPA: the launch's sensors are the rig's sensors at each frame,
+// sensor t * n + s being sensor s at time -t, every one with its own staged
+// region and its frame's temporal factor per radius.
+static lpa_status temporal_impl(lpa_rig* rig, const lpa_frame* frames, int32_t n_times, const lpa_params* params,
+                                const lpa_output* out, void* stream) {
+  if (!rig) return set_error(LPA_ERR_INVALID_ARG, "rig is NULL");
+  lpa_ctx* ctx = rig->ctx;
+  lpa_status st = check_ctx(ctx);
+  if (st != LPA_OK) return st;
+  if (!frames) return set_error(LPA_ERR_INVALID_ARG, "frames is NULL");
+  Resolved R;
+  if ((st = resolve_params(params, &R)) != LPA_OK) return st;
+  if (n_times < 1) return set_error(LPA_ERR_INVALID_ARG, "n_times %d < 1", n_times);
+  if ((int64_t)n_times * rig->n > LPA_MAX_SENSORS)
+    return set_error(LPA_ERR_UNSUPPORTED, "%d frames of %d sensors exceed %d staged sensors", n_times, rig->n,
+                     LPA_MAX_SENSORS);
+  if (R.p.mode != LPA_MODE_LPA || (R.p.flags & LPA_FLAG_PRECOMPUTED_WEIGHTS))
+    return set_error(LPA_ERR_UNSUPPORTED, "temporal LPA takes mode LPA without pre-computed weights");
+  if (R.p.storage != LPA_STORE_FUSED)
+    return set_error(LPA_ERR_UNSUPPORTED, "temporal LPA reads raw frames (storage FUSED)");
+  for (int t = 0; t < n_times; ++t) {
+    if ((st = validate_frame(rig, &frames[t], true)) != LPA_OK) return st;
+    if (frames[t].dtype != frames[0].dtype) return set_error(LPA_ERR_INVALID_ARG, "frames of different dtypes");
+  }
+  if ((st = validate_output(params, out)) != LPA_OK) return st;
+  const double ht_min = (double)(n_times - 1) * (n_times - 1) / 16.0;
+  for (int m = 0; m < R.p.n_scales; ++m) {
+    const double h = R.p.h_t[m];
+    if (!(h >= 0.0) || !std::isfinite(h) || (n_times > 1 && h > 0.0 && h < ht_min))
+      return set_error(LPA_ERR_INVALID_ARG, "h_t[%d] = %g: 0 or at least (n_times - 1)^2 / 16 = %g", m, h, ht_min);
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return device_error(ctx, e, "hipSetDevice");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+
+  std::unique_ptr<lpa_rig> vr(new (std::nothrow) lpa_rig());
+  if (!vr) return set_error(LPA_ERR_OOM, "host allocation failed");
+  vr->ctx = ctx;
+  vr->n = n_times * rig->n;
+  lpa_frame vf{};
+  vf.n_sensors = vr->n;
+  vf.dtype = frames[0].dtype;
+  vf.memory = LPA_MEM_DEVICE;
+  const void* srcs[LPA_MAX_SENSORS];
+  int64_t pitches[LPA_MAX_SENSORS];
+  for (int t = 0; t < n_times; ++t)
+    for (int s = 0; s < rig->n; ++s) {
+      const int v = t * rig->n + s;
+      vr->desc[v] = rig->desc[s];
+      vr->k[v] = rig->k[s];
+      vf.raw[v] = srcs[v] = frames[t].raw[s];
+      vf.row_pitch_bytes[v] = pitches[v] = frames[t].row_pitch_bytes[s];
+    }
+  const int src_kind = vf.dtype == LPA_DTYPE_U16 ? SRC_RAW_U16 : SRC_RAW_F32;
+  LaunchK K;
+  if ((st = build_launch_fit(vr.get(), R, &vf, out, src_kind, srcs, pitches, 16, 16, &K)) != LPA_OK) return st;
+  for (int v = 0; v < vr->n; ++v) {
+    const int t = v / rig->n;
+    K.s[v].time = t;
+    for (int m = 0; m < R.p.n_scales; ++m)
+      K.s[v].kt[m] = t == 0 ? 1.f : (R.p.h_t[m] > 0.0 ? (float)std::exp(-(double)t * t / R.p.h_t[m]) : 0.f);
+  }
+  for (int m = 0; m < R.p.n_scales; ++m) K.sc[m].inv_ht = R.p.h_t[m] > 0.0 ? 1.0 / R.p.h_t[m] : 0.0;
+  K.occupancy = 0;
+
+  void* cbuf = nullptr;
+  void* rbuf = nullptr;
+  size_t cbytes = 0, rbytes = 0;
+  st = stats_begin(ctx, out, &K, hs, &cbuf, &cbytes);
+  if (st == LPA_OK) st = refit_begin(ctx, &K, hs, &rbuf, &rbytes);
+  KernelBracket kb(ctx, hs);
+  if (st == LPA_OK) kb.mark(0);
+  if (st == LPA_OK && lpa_k_fit_temporal(&K, hs) != 0) st = device_error(ctx, hipGetLastError(), "temporal fit launch");
+  if (st == LPA_OK) kb.mark(1);
+  st = refit_end(ctx, K, hs, rbuf, rbytes, st);
+  if (st == LPA_OK) {
+    if (rbuf) kb.mark(2);
+    kb.commit(rbuf != nullptr);
+  }
+  return stats_end(ctx, out, K, hs, cbuf, cbytes, st);
+}
+
 }  // namespace lpa
 
 using namespace lpa;
 
 extern "C" {
+
+lpa_status lpa_reconstruct_temporal(lpa_rig* rig, const lpa_frame* frames, int32_t n_times,
+                                    const lpa_params* params, const lpa_output* out, void* hip_stream) {
+  try {
+    return temporal_impl(rig, frames, n_times, params, out, hip_stream);
+  } catch (...) {
+    return set_error(LPA_ERR_INTERNAL, "unexpected host exception");
+  }
+}
 
 const char* lpa_last_error(void) { return g_last_error; }
 

@@ -52,9 +52,10 @@ struct SensorK {
   const void* raw;
   int64_t raw_pitch;    // bytes
   int32_t raw_f32;      // raw samples are float DN (else uint16)
-  int32_t pad2_;
+  int32_t time;         // temporal LPA: the frame's time is -time (0: the output's frame)
   double gain64, ge64, inv_ge64;  // g, g n, 1 / (g n)
   double black64, read_var64, sat64;
+  float kt[kMaxScales]; // temporal LPA: exp(-time^2 / h_t) per radius (1 at time 0, 0 for h_t = 0)
 };
 
 // Per-scale constants, per channel class (0: R and B, 1: G).
@@ -74,6 +75,7 @@ struct ScaleK {
   // scales it by its own extent).
   float edge_coef[2];
   float mono_r[2];
+  double inv_ht;      // temporal LPA: 1 / h_t (frames^-2) of this radius
 };
 
 // Pre-computed window weights (rigs whose sensor maps and output map are
@@ -203,6 +205,9 @@ int lpa_k_fit_max_lds_bytes(void);
 int lpa_k_grad(const lpa::LaunchK* k, void* stream);
 // Steering pass over the gradient plane.
 int lpa_k_steer(const lpa::SteerArgs* a, void* stream);
+// Temporal LPA: the launch's sensors are (frame, sensor) pairs whose kt and
+// time are set; raw sources only.
+int lpa_k_fit_temporal(const lpa::LaunchK* k, void* stream);
 // Fit with pre-computed window weights read from K.stencil (256-lane tiles).
 int lpa_k_fit_stencil(const lpa::LaunchK* k, void* stream);
 // Fit with per-pixel steered windows read from K.steer.

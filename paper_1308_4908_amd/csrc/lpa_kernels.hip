@@ -96,18 +96,27 @@ __device__ __forceinline__ float window_r2(float dx, float dy, float x2, float y
   else return x2 + y2;
 }
 
-template <int ORDER, bool ICI, bool STEER>
+// TEMP: the window is also scaled by the sample's temporal factor kt (temporal
+// LPA: exp(-t^2 / h_t) of its frame), so K = K_s K_t enters w and the variance
+// moments alike.
+template <int ORDER, bool ICI, bool STEER, bool TEMP = false>
 __device__ __forceinline__ bool acc_sample(Acc<ORDER, ICI>& a, float dx, float dy, float f, float iv,
-                                           float e_edge, float reach2, const SteerC& sc) {
+                                           float e_edge, float reach2, const SteerC& sc, float kt = 1.f) {
   const float x2 = dx * dx, y2 = dy * dy;
   const float r2 = window_r2<STEER>(dx, dy, x2, y2, sc);
   if (r2 < reach2) {
     // K = exp2(-r2) - e_edge never exceeds 1, so clamping to [0, 1] is the
     // cut at zero (one instruction: the subtraction's clamp modifier).
-    const float kw = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-r2) - e_edge, 0.f, 1.f);
+    float kw = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-r2) - e_edge, 0.f, 1.f);
+    // the weight-rounding sums take iv K_t: the window's slope carries K_t
+    float ivt = iv;
+    if constexpr (TEMP) {
+      kw *= kt;
+      ivt *= kt;
+    }
     const float w = kw * iv;
-    a.siv += iv;
-    a.sivf = __builtin_fmaf(iv, fabsf(f), a.sivf);
+    a.siv += ivt;
+    a.sivf = __builtin_fmaf(ivt, fabsf(f), a.sivf);
     if constexpr (ORDER >= 2) {
       // Order 2: the weighted products w d^a for |a| <= 2 are the moments of
       // degree <= 2 and the basis terms of b; each moment of degree 3 and 4 is
@@ -719,7 +728,7 @@ __device__ __forceinline__ float wave_max(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
 }
 
-// Calls fn(dx, dy, f, iv) for every CFA sample of channel c inside the box of
+// Calls fn(dx, dy, f, iv, s) for every CFA sample of channel c inside the box of
 // radius index m around (Xj, Yj), over all sensors (scaled offsets).  The
 // box holds the disk of the radius; for steered windows, the wave's ellipses
 // (half-widths from SteerBox, at most the box of the largest stretch, which
@@ -770,7 +779,8 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
       // row index times pitch: both are below 2^24 (the box lies inside the
       // staged region), so the full-rate 24-bit multiply is exact
       const float2* p0 = plane + __mul24(yb - R.y0, R.w) + (xb - R.x0);
-      walk_box(p0, row_step, nx, ny, c0x, c0y, sax, say, sbx, sby, fn);
+      auto fs = [&](float dx, float dy, float f, float iv) { fn(dx, dy, f, iv, s); };
+      walk_box(p0, row_step, nx, ny, c0x, c0y, sax, say, sbx, sby, fs);
     }
   }
 }
@@ -913,6 +923,10 @@ __device__ double refit_one(const LaunchK& K, const RawT* raw, const Region* reg
     const SensorK& S = K.s[s];
     const Region R = regs[s];
     const RawT* plane = raw + S.lds_off;
+    // the frame's temporal factor exp(-t^2 / h_t) (temporal LPA; 1 at t = 0,
+    // 0 where the FP32 pass has it 0: h_t = 0)
+    const double kt =
+        S.time == 0 ? 1.0 : (S.kt[m] == 0.f ? 0.0 : exp_neg64((double)S.time * S.time * K.sc[m].inv_ht));
     const double px = S.inv[0] * Xj + S.inv[1] * Yj + S.inv[2];
     const double py = S.inv[3] * Xj + S.inv[4] * Yj + S.inv[5];
     const double ax = S.inv[0], ay = S.inv[1], bx = S.inv[3], by = S.inv[4];
@@ -936,7 +950,7 @@ __device__ double refit_one(const LaunchK& K, const RawT* raw, const Region* reg
           if (!(d2 < r2)) continue;
           double f, iv;
           if (decode64(S, (int64_t)y * S.width + x, (double)row[x], f, iv))
-            acc64_d<ORDER>(a, dX, dY, f, (exp_neg64(d2 * ih) - ee) * iv);
+            acc64_d<ORDER>(a, dX, dY, f, (exp_neg64(d2 * ih) - ee) * kt * iv);
         }
       }
     }
@@ -1135,7 +1149,7 @@ __device__ __forceinline__ void walk_stencil(const LaunchK& K, const float2* lds
 
 // cnt64 / cnt_nan count this lane's outputs marked for the FP64 refit and
 // those with no valid fit.
-template <int ORDER, bool ICI, bool STEER, bool STENCIL = false>
+template <int ORDER, bool ICI, bool STEER, bool STENCIL = false, bool TEMP = false>
 __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, const Region* regs,
                                           int u, int v, bool active, int& cnt64, int& cnt_nan) {
   const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
@@ -1189,14 +1203,16 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
         }
       } else if (m == 0) {
         int n = 0;
-        auto accumulate = [&](float dx, float dy, float f, float iv) {
-          n += acc_sample<ORDER, ICI, STEER>(a, dx, dy, f, iv, eedge, reach2, sc) ? 1 : 0;
+        auto accumulate = [&](float dx, float dy, float f, float iv, int s) {
+          n += acc_sample<ORDER, ICI, STEER, TEMP>(a, dx, dy, f, iv, eedge, reach2, sc, TEMP ? K.s[s].kt[m] : 1.f)
+                   ? 1
+                   : 0;
         };
         walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, accumulate);
         n_first = n;
       } else {
-        auto accumulate = [&](float dx, float dy, float f, float iv) {
-          acc_sample<ORDER, ICI, STEER>(a, dx, dy, f, iv, eedge, reach2, sc);
+        auto accumulate = [&](float dx, float dy, float f, float iv, int s) {
+          acc_sample<ORDER, ICI, STEER, TEMP>(a, dx, dy, f, iv, eedge, reach2, sc, TEMP ? K.s[s].kt[m] : 1.f);
         };
         walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, accumulate);
       }
@@ -1251,11 +1267,13 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
           Acc64<ORDER> a64;
           acc64_zero(a64);
           int n = 0;
-          auto second = [&](float dx, float dy, float f, float iv) {
+          auto second = [&](float dx, float dy, float f, float iv, int s) {
             (void)f;
             const float r2 = window_r2<STEER>(dx, dy, dx * dx, dy * dy, sc);
             if (r2 < reach2) {
-              const float w = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f, 1.f) * iv;
+              float kw = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f, 1.f);
+              if constexpr (TEMP) kw *= K.s[s].kt[m];
+              const float w = kw * iv;
               n += (w > 0.f) ? 1 : 0;
               acc64_sample<ORDER, false>(a64, dx, dy, 0.f, w, hi);
             }
@@ -1284,11 +1302,12 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
               ys[o] = 0.0;
               vs[o] = 0.f;
             }
-            auto third = [&](float dx, float dy, float f, float iv) {
+            auto third = [&](float dx, float dy, float f, float iv, int s) {
               const float x2 = dx * dx, y2 = dy * dy;
               const float r2 = window_r2<STEER>(dx, dy, x2, y2, sc);
               if (r2 < reach2) {
-                const float kw = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f, 1.f);
+                float kw = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f, 1.f);
+                if constexpr (TEMP) kw *= K.s[s].kt[m];
                 const float w = kw * iv;
                 const double x = dx, y = dy, wf = (double)w * (double)f;
                 const double phi[6] = {1.0, x, y, x * x, x * y, y * y};
@@ -1368,7 +1387,7 @@ struct TileShared {
   uint32_t stat[2];  // the tile's FP64-valued and no-data outputs
 };
 
-template <int ORDER, bool ICI, int SRC, bool STEER = false, bool STENCIL = false>
+template <int ORDER, bool ICI, int SRC, bool STEER = false, bool STENCIL = false, bool TEMP = false>
 __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2* lds, TileShared& sh) {
   const int tx = tile % K.tiles_x;
   const int ty = tile / K.tiles_x;
@@ -1384,7 +1403,7 @@ __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2*
   const bool active = (u < K.out_w) && (v < K.out_h);
   // inactive lanes of a ragged tile compute at their nominal pixel (staged)
   int cnt64 = 0, cnt_nan = 0;
-  fit_pixel<ORDER, ICI, STEER, STENCIL>(K, lds, sh.regs, u, v, active, cnt64, cnt_nan);
+  fit_pixel<ORDER, ICI, STEER, STENCIL, TEMP>(K, lds, sh.regs, u, v, active, cnt64, cnt_nan);
   if (K.tile_stats) {
     if (cnt64) atomicAdd(&sh.stat[0], (uint32_t)cnt64);
     if (cnt_nan) atomicAdd(&sh.stat[1], (uint32_t)cnt_nan);
@@ -1414,6 +1433,17 @@ fit_kernel_occ4(const LaunchK K) {
   extern __shared__ float2 lds[];
   __shared__ TileShared sh;
   process_tile<ORDER, ICI, SRC>(K, xcd_tile(blockIdx.x, gridDim.x), lds, sh);
+}
+
+// Temporal LPA: the launch's sensors are the rig's sensors at several frames
+// (one staged region each), every sample's window scaled by its frame's
+// temporal factor.
+template <int ORDER, bool ICI, int SRC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+fit_kernel_temporal(const LaunchK K) {
+  extern __shared__ float2 lds[];
+  __shared__ TileShared sh;
+  process_tile<ORDER, ICI, SRC, false, false, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1528,7 +1558,7 @@ __global__ void __launch_bounds__(256) grad_kernel(const LaunchK K) {
 #pragma unroll
   for (int k = 0; k < n_basis<ORDER>(); ++k) b64[k] = 0.0;
   int n = 0;
-  auto accumulate = [&](float dx, float dy, float f, float iv) {
+  auto accumulate = [&](float dx, float dy, float f, float iv, int s) {
     const float r2 = dx * dx + dy * dy;
     if (r2 < reach2) {
       const float w = fmaxf(__builtin_amdgcn_exp2f(-r2) - eedge, 0.f) * iv;
@@ -1866,6 +1896,35 @@ extern "C" int lpa_k_fit(const LaunchK* k, void* stream) {
     case 3: return launch_fit_src<1, true>(K, st);
     case 4: return launch_fit_src<2, false>(K, st);
     case 5: return launch_fit_src<2, true>(K, st);
+    default: return -1;
+  }
+}
+
+namespace {
+template <int ORDER, bool ICI>
+int launch_temporal_src(const LaunchK& K, hipStream_t st) {
+  const dim3 grid(K.tiles_x * K.tiles_y), block(K.tile_w * K.tile_h);
+  const size_t lds = (size_t)K.lds_floats2 * sizeof(float2);
+  switch (K.src_kind) {
+    case SRC_RAW_U16: fit_kernel_temporal<ORDER, ICI, SRC_RAW_U16><<<grid, block, lds, st>>>(K); break;
+    case SRC_RAW_F32: fit_kernel_temporal<ORDER, ICI, SRC_RAW_F32><<<grid, block, lds, st>>>(K); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+}  // namespace
+
+extern "C" int lpa_k_fit_temporal(const LaunchK* k, void* stream) {
+  const LaunchK& K = *k;
+  if (!raw_bound(K) || K.tile_w * K.tile_h > 256 || (size_t)K.lds_floats2 * sizeof(float2) > (size_t)kMaxLdsBytes) return -1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (K.order * 2 + (K.need_var ? 1 : 0)) {
+    case 0: return launch_temporal_src<0, false>(K, st);
+    case 1: return launch_temporal_src<0, true>(K, st);
+    case 2: return launch_temporal_src<1, false>(K, st);
+    case 3: return launch_temporal_src<1, true>(K, st);
+    case 4: return launch_temporal_src<2, false>(K, st);
+    case 5: return launch_temporal_src<2, true>(K, st);
     default: return -1;
   }
 }

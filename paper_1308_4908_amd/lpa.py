@@ -66,6 +66,7 @@ class Params(ctypes.Structure):
         ("pad_", ctypes.c_int32), ("alpha", ctypes.c_double), ("lambda1", ctypes.c_double),
         ("lambda2", ctypes.c_double), ("grad_radius", ctypes.c_double), ("grad_h", ctypes.c_double),
         ("max_stretch", ctypes.c_double), ("value_tol", ctypes.c_double),
+        ("h_t", ctypes.c_double * MAX_SCALES),
     ]
 
 
@@ -135,6 +136,8 @@ SIGNATURES = {
                                       ctypes.POINTER(TuneResult)]),
     "lpa_tuner_save": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_char_p]),
     "lpa_tuner_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_char_p]),
+    "lpa_reconstruct_temporal": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Frame), ctypes.c_int32,
+                                                  ctypes.POINTER(Params), ctypes.POINTER(Output), ctypes.c_void_p]),
     "lpa_set_kernel_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "lpa_kernel_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(KernelTime)]),
     "lpa_last_error": (ctypes.c_char_p, []),
@@ -189,6 +192,7 @@ lpa_drain = _c("lpa_drain")
 lpa_autotune = _c("lpa_autotune")
 lpa_tuner_save = _c("lpa_tuner_save")
 lpa_tuner_load = _c("lpa_tuner_load")
+lpa_reconstruct_temporal = _c("lpa_reconstruct_temporal")
 lpa_set_kernel_timing = _c("lpa_set_kernel_timing")
 lpa_kernel_times = _c("lpa_kernel_times")
 lpa_last_error = _c("lpa_last_error")
@@ -269,6 +273,11 @@ def params_struct(p: dict) -> Params:
     q.grad_order = int(ad.get("grad_order", 0))
     q.grad_halfwin = int(ad.get("grad_halfwin", 2))
     q.value_tol = float(p.get("value_tol", 0.0))
+    hts = list(p.get("h_t") or [])
+    if hts and len(hts) != len(radii):
+        raise ValueError("h_t must give one value per radius")
+    for i, ht in enumerate(hts):
+        q.h_t[i] = float(ht)
     return q
 
 
@@ -444,6 +453,17 @@ class Rig:
         ou = output_struct(out, scale_map, sd_map, grad_map, steer_map, stats)
         fn = lpa_reconstruct_plain if plain else (lpa_reconstruct_noalloc if noalloc else lpa_reconstruct)
         check(fn(self.handle, ctypes.byref(fr), ctypes.byref(pr), ctypes.byref(ou), _stream_handle(stream)))
+
+    def reconstruct_temporal(self, frames, params: dict, out, scale_map=None, stream=None, sd_map=None,
+                             stats=None):
+        """Temporal LPA: frames[t] holds the sensors' raw planes at time -t
+        (frames[0] is reconstructed); params["h_t"] one temporal scale per radius."""
+        n = len(frames)
+        fr = (Frame * n)(*[frame_struct(f) for f in frames])
+        pr = params_struct(params)
+        ou = output_struct(out, scale_map, sd_map, stats=stats)
+        check(lpa_reconstruct_temporal(self.handle, fr, n, ctypes.byref(pr), ctypes.byref(ou),
+                                       _stream_handle(stream)))
 
     def autotune(self, raws, params: dict, out, reps: int = 3, stream=None) -> TuneResult:
         """Time every launch-shape candidate on this frame; keep the fastest for its class."""
