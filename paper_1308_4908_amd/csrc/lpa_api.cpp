@@ -27,9 +27,16 @@ lpa_status set_error(lpa_status st, const char* fmt, ...) {
 }
 
 lpa_status device_error(lpa_ctx* ctx, hipError_t e, const char* what) {
-  if (ctx) ctx->failed.store(true);
   (void)hipGetLastError();  // leave no error state behind for the caller's own HIP calls
-  return set_error(LPA_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  const lpa_status st = set_error(LPA_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  if (ctx) {
+    // the first failure's message, for every later refusal (it may have
+    // happened on the serving thread)
+    std::lock_guard<std::mutex> g(ctx->fail_mu);
+    if (!ctx->failed.load()) std::snprintf(ctx->fail_msg, sizeof(ctx->fail_msg), "%s", g_last_error);
+    ctx->failed.store(true);
+  }
+  return st;
 }
 
 // Colour (0 R, 1 G, 2 B) of CFA cell [2 * row parity + column parity].
@@ -406,7 +413,10 @@ lpa_status build_launch_fit(const lpa_rig* rig, const Resolved& R, const lpa_fra
 
 lpa_status check_ctx(lpa_ctx* ctx) {
   if (!ctx) return set_error(LPA_ERR_INVALID_ARG, "context is NULL");
-  if (ctx->failed.load()) return set_error(LPA_ERR_DEVICE, "context failed after an earlier device error");
+  if (ctx->failed.load()) {
+    std::lock_guard<std::mutex> g(ctx->fail_mu);
+    return set_error(LPA_ERR_DEVICE, "context failed after an earlier device error (%s)", ctx->fail_msg);
+  }
   return LPA_OK;
 }
 
@@ -437,7 +447,7 @@ void free_async(lpa_ctx* ctx, void* p, size_t bytes, hipStream_t st, bool charge
 
 // Pre-pass every sensor into planes; fills srcs/pitches and the allocations.
 lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_t st, void** planes,
-                       size_t* plane_bytes, const void** srcs, int64_t* pitches, bool charge) {
+                       size_t* plane_bytes, const void** srcs, int64_t* pitches, bool charge, bool launch) {
   lpa_ctx* ctx = rig->ctx;
   for (int s = 0; s < rig->n; ++s) {
     const SensorK& S = rig->k[s];
@@ -446,8 +456,8 @@ lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_
     lpa_status rs = alloc_async(ctx, plane_bytes[s], st, &planes[s], charge);
     if (rs != LPA_OK) return rs;
     const float enc = std::ldexp(1.0f, -rig->desc[s].bit_depth);
-    if (lpa_k_prepass(&S, f->dtype == LPA_DTYPE_F32, f->raw[s], f->row_pitch_bytes[s], planes[s], pitch,
-                      to_f16 ? 1 : 0, enc, st) != 0)
+    if (launch && lpa_k_prepass(&S, f->dtype == LPA_DTYPE_F32, f->raw[s], f->row_pitch_bytes[s], planes[s], pitch,
+                                to_f16 ? 1 : 0, enc, st) != 0)
       return device_error(ctx, hipGetLastError(), "pre-pass launch");
     srcs[s] = planes[s];
     pitches[s] = pitch;

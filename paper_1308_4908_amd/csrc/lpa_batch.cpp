@@ -91,7 +91,9 @@ lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_f
       size_t pb[LPA_MAX_SENSORS] = {0};
       const void* srcs[LPA_MAX_SENSORS];
       int64_t pitches[LPA_MAX_SENSORS];
-      lpa_status st = run_prepass(rigs[i], &frames[i], sk == SRC_PLANE_F16, stream, pl, pb, srcs, pitches, charge);
+      // the planes only: the batch graph's pre-pass node fills them
+      lpa_status st =
+          run_prepass(rigs[i], &frames[i], sk == SRC_PLANE_F16, stream, pl, pb, srcs, pitches, charge, false);
       for (int s = 0; s < rigs[i]->n; ++s)
         if (pl[s]) planes->push_back({pl[s], pb[s]});
       if (st != LPA_OK) return st;
@@ -109,6 +111,8 @@ lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
 
 static void slot_release(BatchSlot& sl) {
   if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+  if (sl.graph) (void)hipGraphDestroy(sl.graph);
+  sl.graph = nullptr;
   if (sl.h_buf) (void)hipHostFree(sl.h_buf);
   if (sl.d_buf) (void)hipFree(sl.d_buf);
   sl.exec = nullptr;
@@ -210,26 +214,43 @@ lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
     first[i] = acc;
     acc += (int64_t)ks[i].tiles_x * ks[i].tiles_y;
   }
-  const int64_t sig[5] = {src_kind, block, lds, grid, sl.cap};
-  if (!sl.exec || std::memcmp(sig, sl.sig, sizeof(sig)) != 0) {
-    if (sl.exec) {
-      (void)hipGraphExecDestroy(sl.exec);
-      sl.exec = nullptr;
+  // The graph depends on the source kind, block, grid and capacity; a batch
+  // whose frames need another LDS size updates the two kernel nodes of the
+  // instantiated graph.
+  const int64_t sig[4] = {src_kind, block, grid, sl.cap};
+  char* d = static_cast<char*>(sl.d_buf);
+  const auto* d_hdr = reinterpret_cast<const BatchHeader*>(d);
+  const auto* d_frames = reinterpret_cast<const LaunchK*>(d + L.frames_off);
+  const auto* d_first = reinterpret_cast<const int64_t*>(d + L.first_off);
+  auto* d_queue = reinterpret_cast<int32_t*>(d + L.queue_off);
+  const int refit_grid = ctx->n_cu * 8;
+  bool rebuild = !sl.exec || std::memcmp(sig, sl.sig, sizeof(sig)) != 0;
+  if (!rebuild && sl.lds != lds) {
+    // another LDS size: update the two nodes in place; a runtime that refuses
+    // the update gets a new graph instead
+    if (lpa_k_batch_graph_set_lds(sl.exec, sl.fit_node, sl.refit_node, d_hdr, d_frames, d_first, d_queue, src_kind,
+                                  block, lds, grid, refit_grid) == 0)
+      sl.lds = lds;
+    else {
+      (void)hipGetLastError();
+      rebuild = true;
     }
-    char* d = static_cast<char*>(sl.d_buf);
-    hipGraph_t graph = nullptr;
-    if (lpa_k_batch_graph(&graph, d, h, L.copy_bytes, reinterpret_cast<const BatchHeader*>(d),
-                          reinterpret_cast<const LaunchK*>(d + L.frames_off),
-                          reinterpret_cast<const int64_t*>(d + L.first_off), reinterpret_cast<int32_t*>(d + L.queue_off),
-                          src_kind, block, lds, grid, ctx->n_cu * 8, sl.cap) != 0)
+  }
+  if (rebuild) {
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    if (sl.graph) (void)hipGraphDestroy(sl.graph);
+    sl.exec = nullptr;
+    sl.graph = nullptr;
+    if (lpa_k_batch_graph(&sl.graph, &sl.fit_node, &sl.refit_node, d, h, L.copy_bytes, d_hdr, d_frames, d_first,
+                          d_queue, src_kind, block, lds, grid, refit_grid, sl.cap) != 0)
       return device_error(ctx, hipGetLastError(), "batch graph");
-    e = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
+    e = hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
       sl.exec = nullptr;
       return device_error(ctx, e, "graph instantiate");
     }
     std::memcpy(sl.sig, sig, sizeof(sig));
+    sl.lds = lds;
   }
   if ((e = hipGraphLaunch(sl.exec, stream)) != hipSuccess) return device_error(ctx, e, "graph launch");
   if ((e = hipEventRecord(sl.done, stream)) != hipSuccess) return device_error(ctx, e, "event record");

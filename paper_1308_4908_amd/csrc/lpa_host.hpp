@@ -102,7 +102,10 @@ struct BatchSlot {
   hipEvent_t done = nullptr;
   bool used = false;
   hipGraphExec_t exec = nullptr;
-  int64_t sig[5] = {0, 0, 0, 0, 0};
+  hipGraph_t graph = nullptr;     // kept with exec: its node handles name the nodes to update
+  hipGraphNode_t fit_node = nullptr, refit_node = nullptr;
+  int64_t sig[4] = {0, 0, 0, 0};  // source kind, block, grid, capacity
+  int lds = 0;                    // dynamic LDS of the fit node (float2 elements)
 };
 
 // Byte layout of a batch table of capacity cap.
@@ -127,6 +130,8 @@ struct lpa_ctx {
   size_t budget = 0;
   std::atomic<size_t> used{0};
   std::atomic<bool> failed{false};
+  std::mutex fail_mu;
+  char fail_msg[256] = {0};  // message of the first device error
   lpa::Tuner tuner;
   // batch path: a ring of reusable tables, each with its graph
   std::mutex batch_mu;
@@ -184,8 +189,12 @@ lpa_status build_launch_fit(const lpa_rig* rig, const Resolved& R, const lpa_fra
 // (the serving scheduler charges a frame's whole footprint at admission).
 lpa_status alloc_async(lpa_ctx* ctx, size_t bytes, hipStream_t st, void** p, bool charge = true);
 void free_async(lpa_ctx* ctx, void* p, size_t bytes, hipStream_t st, bool charge = true);
+// Allocates a frame's pre-pass planes (stream-ordered) and, with `launch`,
+// enqueues the pre-pass of every sensor; batches leave `launch` off, their
+// graph fills the planes.
 lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_t st, void** planes,
-                       size_t* plane_bytes, const void** srcs, int64_t* pitches, bool charge = true);
+                       size_t* plane_bytes, const void** srcs, int64_t* pitches, bool charge = true,
+                       bool launch = true);
 // Pre-computed-weight table of a launch (lpa_stencil.cpp): checks that every
 // sensor map and the output map are translations, then returns the rig's
 // cached device table for the launch's radii and windows, building it on

@@ -223,10 +223,17 @@ int lpa_k_refit_batch(const lpa::BatchHeader* hdr, const lpa::LaunchK* frames, c
 // from pinned h_table to d_table, which holds d_hdr / d_frames / d_first),
 // queue reset, persistent fit (grid x block, lds_floats2 float2 of LDS), FP64
 // refit (refit_grid workgroups) and count reduction (cap workgroups).
-int lpa_k_batch_graph(hipGraph_t* out, void* d_table, const void* h_table, size_t copy_bytes,
-                      const lpa::BatchHeader* d_hdr, const lpa::LaunchK* d_frames, const int64_t* d_first,
-                      int32_t* d_queue, int32_t src_kind, int32_t block, int32_t lds_floats2, int32_t grid,
-                      int32_t refit_grid, int32_t cap);
+// The fit and refit nodes are returned so that a launch whose frames need
+// another LDS size can update them in the instantiated graph
+// (lpa_k_batch_graph_set_lds) instead of building a new one.
+int lpa_k_batch_graph(hipGraph_t* out, hipGraphNode_t* fit_node, hipGraphNode_t* refit_node, void* d_table,
+                      const void* h_table, size_t copy_bytes, const lpa::BatchHeader* d_hdr,
+                      const lpa::LaunchK* d_frames, const int64_t* d_first, int32_t* d_queue, int32_t src_kind,
+                      int32_t block, int32_t lds_floats2, int32_t grid, int32_t refit_grid, int32_t cap);
+int lpa_k_batch_graph_set_lds(hipGraphExec_t exec, hipGraphNode_t fit_node, hipGraphNode_t refit_node,
+                              const lpa::BatchHeader* d_hdr, const lpa::LaunchK* d_frames, const int64_t* d_first,
+                              int32_t* d_queue, int32_t src_kind, int32_t block, int32_t lds_floats2, int32_t grid,
+                              int32_t refit_grid);
 // Zero n ints with a small kernel (graph-safe replacement for a memset).
 int lpa_k_zero_i32(int32_t* p, int32_t n, void* stream);
 // Sum a frame's per-tile counts (n_tiles pairs) into out[0], out[1].

@@ -1735,6 +1735,41 @@ __global__ void __launch_bounds__(256) prepass_kernel(const SensorK S, const voi
   }
 }
 
+// The pre-pass of a whole batch (plane storage forms), one launch inside the
+// batch graph: workgroup row blockIdx.y is frame y / kMaxSensors, sensor
+// y % kMaxSensors of the batch table; its workgroups stride over that
+// sensor's rows, 256 lanes along a row.  Reads each frame's raw plane
+// (S.raw) and writes the plane the fit reads (S.src, allocated by the library
+// for this launch).
+template <bool TO_F16>
+__global__ void __launch_bounds__(256) prepass_batch_kernel(const BatchHeader* __restrict__ hdr,
+                                                            const LaunchK* __restrict__ frames) {
+  const int f = blockIdx.y / kMaxSensors, s = blockIdx.y % kMaxSensors;
+  if (f >= hdr->n_frames) return;
+  const LaunchK& K = frames[f];
+  if (s >= K.n_sensors) return;
+  const SensorK& S = K.s[s];
+  const bool raw_f32 = S.raw_f32 != 0;
+  const bool cal = S.calib != nullptr;
+  const float norm_encode = 1.f / S.norm_decode;  // a power of two: exact
+  for (int y = blockIdx.x; y < S.height; y += gridDim.x) {
+    const char* rrow = static_cast<const char*>(S.raw) + (int64_t)y * S.raw_pitch;
+    char* prow = static_cast<char*>(const_cast<void*>(S.src)) + (int64_t)y * S.pitch;
+    for (int x = threadIdx.x; x < S.width; x += 256) {
+      const float dn = raw_f32 ? reinterpret_cast<const float*>(rrow)[x]
+                               : (float)reinterpret_cast<const uint16_t*>(rrow)[x];
+      const float4 c = cal ? S.calib[(int64_t)y * S.width + x] : make_float4(S.black, S.inv_ge, S.read_var, S.sat);
+      if constexpr (TO_F16) {
+        const __half h = (dn < c.w) ? __float2half_rn((dn - S.norm_offset) * norm_encode)
+                                    : __ushort_as_half((unsigned short)0x7C00u);
+        reinterpret_cast<__half*>(prow)[x] = h;
+      } else {
+        reinterpret_cast<float2*>(prow)[x] = cal ? decode_dn_cal(S, dn, c) : decode_dn(S, dn);
+      }
+    }
+  }
+}
+
 }  // namespace lpa
 
 using namespace lpa;
@@ -2058,10 +2093,51 @@ extern "C" int lpa_k_zero_i32(int32_t* p, int32_t n, void* stream) {
 // mode, so other threads' device-wide calls never meet a capturing stream):
 // the table copy from pinned host memory, the queue reset, the persistent fit,
 // the FP64 refit and the count reduction, in that order.
-extern "C" int lpa_k_batch_graph(hipGraph_t* out, void* d_table, const void* h_table, size_t copy_bytes,
-                                 const BatchHeader* d_hdr, const LaunchK* d_frames, const int64_t* d_first,
-                                 int32_t* d_queue, int32_t src_kind, int32_t block, int32_t lds_floats2,
-                                 int32_t grid, int32_t refit_grid, int32_t cap) {
+namespace {
+// Kernel-node arguments of a batch graph (the values the parameter arrays
+// point at live here while a node is added or updated).
+struct BatchNodeArgs {
+  const BatchHeader* hdr;
+  const LaunchK* frames;
+  const int64_t* first;
+  int32_t* queue;
+  void* fit[4];
+  void* refit[3];
+  BatchNodeArgs(const BatchHeader* h, const LaunchK* f, const int64_t* fi, int32_t* q)
+      : hdr(h), frames(f), first(fi), queue(q), fit{&hdr, &frames, &first, &queue}, refit{&hdr, &frames, &first} {}
+};
+
+bool batch_fit_params(BatchNodeArgs& a, int32_t src_kind, int32_t block, int32_t lds_floats2, int32_t grid,
+                      hipKernelNodeParams* p) {
+  *p = hipKernelNodeParams{};
+  switch (src_kind) {
+    case SRC_RAW_U16: p->func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_RAW_U16>); break;
+    case SRC_RAW_F32: p->func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_RAW_F32>); break;
+    case SRC_PLANE_F32: p->func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_PLANE_F32>); break;
+    case SRC_PLANE_F16: p->func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_PLANE_F16>); break;
+    default: return false;
+  }
+  p->gridDim = dim3(grid);
+  p->blockDim = dim3(block);
+  p->sharedMemBytes = (unsigned)((size_t)lds_floats2 * sizeof(float2));
+  p->kernelParams = a.fit;
+  return true;
+}
+
+void batch_refit_params(BatchNodeArgs& a, int32_t lds_floats2, int32_t refit_grid, hipKernelNodeParams* p) {
+  *p = hipKernelNodeParams{};
+  p->func = reinterpret_cast<void*>(&refit_batch_kernel);
+  p->gridDim = dim3(refit_grid);
+  p->blockDim = dim3(kRefitBlock);
+  p->sharedMemBytes = (unsigned)((size_t)lds_floats2 * 4);
+  p->kernelParams = a.refit;
+}
+}  // namespace
+
+extern "C" int lpa_k_batch_graph(hipGraph_t* out, hipGraphNode_t* fit_node, hipGraphNode_t* refit_node,
+                                 void* d_table, const void* h_table, size_t copy_bytes, const BatchHeader* d_hdr,
+                                 const LaunchK* d_frames, const int64_t* d_first, int32_t* d_queue, int32_t src_kind,
+                                 int32_t block, int32_t lds_floats2, int32_t grid, int32_t refit_grid, int32_t cap) {
   *out = nullptr;
   hipGraph_t g = nullptr;
   if (hipGraphCreate(&g, 0) != hipSuccess) return -2;
@@ -2076,28 +2152,29 @@ extern "C" int lpa_k_batch_graph(hipGraph_t* out, void* d_table, const void* h_t
   p.sharedMemBytes = 0;
   p.kernelParams = zero_args;
   p.extra = nullptr;
-  if (e == hipSuccess) e = hipGraphAddKernelNode(&n_zero, g, &n_copy, 1, &p);
-  void* fit_args[] = {&d_hdr, &d_frames, &d_first, &d_queue};
-  switch (src_kind) {
-    case SRC_RAW_U16: p.func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_RAW_U16>); break;
-    case SRC_RAW_F32: p.func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_RAW_F32>); break;
-    case SRC_PLANE_F32: p.func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_PLANE_F32>); break;
-    case SRC_PLANE_F16: p.func = reinterpret_cast<void*>(&fit_batch_kernel<SRC_PLANE_F16>); break;
-    default: e = hipErrorInvalidValue;
+  // plane storage: every frame's pre-pass between the table copy and the fit
+  hipGraphNode_t n_first = n_copy;
+  if (src_kind == SRC_PLANE_F32 || src_kind == SRC_PLANE_F16) {
+    hipGraphNode_t n_pre = nullptr;
+    void* pre_args[] = {&d_hdr, &d_frames};
+    hipKernelNodeParams q{};
+    q.func = src_kind == SRC_PLANE_F16 ? reinterpret_cast<void*>(&prepass_batch_kernel<true>)
+                                       : reinterpret_cast<void*>(&prepass_batch_kernel<false>);
+    q.gridDim = dim3(64, (unsigned)cap * kMaxSensors);
+    q.blockDim = dim3(256);
+    q.sharedMemBytes = 0;
+    q.kernelParams = pre_args;
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&n_pre, g, &n_copy, 1, &q);
+    n_first = n_pre;
   }
-  p.gridDim = dim3(grid);
-  p.blockDim = dim3(block);
-  p.sharedMemBytes = (unsigned)((size_t)lds_floats2 * sizeof(float2));
-  p.kernelParams = fit_args;
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n_zero, g, &n_first, 1, &p);
+  BatchNodeArgs args(d_hdr, d_frames, d_first, d_queue);
+  if (e == hipSuccess && !batch_fit_params(args, src_kind, block, lds_floats2, grid, &p)) e = hipErrorInvalidValue;
   if (e == hipSuccess) e = hipGraphAddKernelNode(&n_fit, g, &n_zero, 1, &p);
-  void* refit_args[] = {&d_hdr, &d_frames, &d_first};
-  p.func = reinterpret_cast<void*>(&refit_batch_kernel);
-  p.gridDim = dim3(refit_grid);
-  p.blockDim = dim3(kRefitBlock);
-  p.sharedMemBytes = (unsigned)((size_t)lds_floats2 * 4);
-  p.kernelParams = refit_args;
+  batch_refit_params(args, lds_floats2, refit_grid, &p);
   if (e == hipSuccess) e = hipGraphAddKernelNode(&n_refit, g, &n_fit, 1, &p);
   void* stats_args[] = {&d_hdr, &d_frames};
+  p = hipKernelNodeParams{};
   p.func = reinterpret_cast<void*>(&stats_frames_kernel);
   p.gridDim = dim3(cap);
   p.blockDim = dim3(256);
@@ -2109,5 +2186,20 @@ extern "C" int lpa_k_batch_graph(hipGraph_t* out, void* d_table, const void* h_t
     return -2;
   }
   *out = g;
+  *fit_node = n_fit;
+  *refit_node = n_refit;
+  return 0;
+}
+
+extern "C" int lpa_k_batch_graph_set_lds(hipGraphExec_t exec, hipGraphNode_t fit_node, hipGraphNode_t refit_node,
+                                         const BatchHeader* d_hdr, const LaunchK* d_frames, const int64_t* d_first,
+                                         int32_t* d_queue, int32_t src_kind, int32_t block, int32_t lds_floats2,
+                                         int32_t grid, int32_t refit_grid) {
+  BatchNodeArgs args(d_hdr, d_frames, d_first, d_queue);
+  hipKernelNodeParams p{};
+  if (!batch_fit_params(args, src_kind, block, lds_floats2, grid, &p)) return -1;
+  if (hipGraphExecKernelNodeSetParams(exec, fit_node, &p) != hipSuccess) return -2;
+  batch_refit_params(args, lds_floats2, refit_grid, &p);
+  if (hipGraphExecKernelNodeSetParams(exec, refit_node, &p) != hipSuccess) return -2;
   return 0;
 }

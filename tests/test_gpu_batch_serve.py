@@ -95,6 +95,40 @@ def test_batch_equals_alone_across_replays(torch_mod, storage):
     ctx.close()
 
 
+def test_batch_graph_reused_across_lds_sizes(torch_mod):
+    """Consecutive batches of frames that need different LDS sizes (2- and
+    4-sensor frames) replay each slot's graph with its kernel nodes updated:
+    10 launches over the 4 slots, every frame equal to its result alone."""
+    torch = torch_mod
+    from paper_1308_4908_amd import Context, Rig
+
+    ctx = Context(0)
+    frames = make_frames(6, seed0=4300)
+    sets = [[0, 3], [2, 5], [1, 4]]  # 2 sensors, 4 sensors, 3 sensors
+    rigs, devs, params, refs = [], [], [], []
+    for sensors, raws, p in frames:
+        rig = Rig(ctx, sensors)
+        dev = [torch.from_numpy(r).cuda() for r in raws]
+        rigs.append(rig)
+        devs.append(dev)
+        params.append(p)
+        refs.append(alone(torch, ctx, rig, dev, p))
+    for launch in range(10):
+        sel = sets[launch % 3]
+        outs = [torch.full((params[i]["out_h"], params[i]["out_w"], 3), -1.0, device="cuda") for i in sel]
+        maps = [torch.zeros((params[i]["out_h"], params[i]["out_w"], 3), dtype=torch.uint8, device="cuda")
+                for i in sel]
+        _say(f"[gpu] batch launch {launch}: frames {sel}")
+        ctx.reconstruct_batch([rigs[i] for i in sel], [devs[i] for i in sel], [params[i] for i in sel], outs, maps)
+        torch.cuda.synchronize()
+        for k, i in enumerate(sel):
+            assert np.array_equal(outs[k].cpu().numpy(), refs[i][0], equal_nan=True), f"frame {i} launch {launch}"
+            assert np.array_equal(maps[k].cpu().numpy(), refs[i][1]), f"frame {i} launch {launch}"
+    for r in rigs:
+        r.close()
+    ctx.close()
+
+
 def _serve(torch, ctx, items, host_pinned=True):
     """Submit items = [(rig, raws_np, params)] as fast as possible; returns outputs and results."""
     outs, tickets, hosts = [], [], []
