@@ -331,7 +331,12 @@ lpa_status lpa_submit(lpa_rig* rig, const lpa_frame* frame, const lpa_params* pa
  * handed out once: the ticket is forgotten after that (a later poll returns
  * LPA_ERR_INVALID_ARG), so the context keeps no record of collected frames. */
 lpa_status lpa_poll(lpa_ctx* ctx, uint64_t ticket, lpa_result* out);
-/* Block until every submitted frame is finished. */
+/* Block until every submitted frame is finished.  After a device error the
+ * context is failed: frames not yet launched finish with LPA_ERR_DEVICE,
+ * submissions are refused, and the context is to be destroyed (a new one
+ * can be created on the device).  For tests, the environment variable
+ * LPA_TEST_FAIL_AFTER=N, read when a context is created, makes its N-th
+ * serving batch launch fail this way from the host, before any GPU work. */
 lpa_status lpa_drain(lpa_ctx* ctx);
 
 /* Autotuning (launch shape only; results never depend on it).  Candidates:

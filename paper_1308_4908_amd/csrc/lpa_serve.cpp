@@ -17,8 +17,10 @@
 // same frame reconstructed alone.
 #include <algorithm>
 #include <chrono>
-#include <map>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 
 #include "lpa_host.hpp"
 
@@ -107,6 +109,11 @@ struct Scheduler {
   uint64_t* d_stats[2] = {nullptr, nullptr};
   uint64_t* h_stats[2] = {nullptr, nullptr};
   std::thread worker;
+  // failure injection for tests (LPA_TEST_FAIL_AFTER=N at context creation):
+  // the N-th batch launch fails from the host, before anything is enqueued,
+  // as a device error would (the context fails, pending frames end with it)
+  int64_t fail_after = 0;
+  int64_t launches = 0;
   static constexpr size_t kQueueCap = 1024;
   static constexpr int kMaxInflight = 2;
   static constexpr int kMaxBatch = 64;
@@ -226,9 +233,13 @@ struct Scheduler {
     std::vector<LaunchK> ks;
     int sk = 0;
     const int64_t t = now_ns();
+    lpa_status s = LPA_OK;
+    if (fail_after > 0 && ++launches >= fail_after)
+      s = device_error(ctx, hipErrorUnknown, "failure injected by LPA_TEST_FAIL_AFTER");
     // the frame footprints were charged at admission: plane scratch is not charged again
-    lpa_status s = prepare_frames(ctx, take, rigs.data(), frames.data(), params.data(), outs.data(), st, &ks, &sk,
-                                  &b.planes, false);
+    if (s == LPA_OK)
+      s = prepare_frames(ctx, take, rigs.data(), frames.data(), params.data(), outs.data(), st, &ks, &sk, &b.planes,
+                         false);
     if (s == LPA_OK) s = launch_batch(ctx, ks, sk, st, false);
     for (const PlaneAlloc& p : b.planes) free_async(ctx, p.p, p.bytes, st, false);
     b.planes.clear();
@@ -278,11 +289,29 @@ struct Scheduler {
     return any;
   }
 
+  // Once the context has failed, frames not yet launched end with its error
+  // (batches in flight still retire when their events complete).
+  void fail_pending() {
+    char msg[sizeof(g_last_error)];
+    {
+      std::lock_guard<std::mutex> g(ctx->fail_mu);
+      std::snprintf(msg, sizeof(msg), "context failed after an earlier device error (%s)", ctx->fail_msg);
+    }
+    while (!waiting.empty() || !admitted.empty()) {
+      std::deque<Request*>& q = waiting.empty() ? admitted : waiting;
+      Request* r = q.front();
+      q.pop_front();
+      set_error(LPA_ERR_DEVICE, "%s", msg);
+      finish(r, LPA_ERR_DEVICE);
+    }
+  }
+
   void run() {
     (void)hipSetDevice(ctx->device);
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
       const bool retired = retire();
+      if (ctx->failed.load()) fail_pending();
       admit();
       while (!admitted.empty() && (int)inflight.size() < kMaxInflight) launch();
       if (retired) cv_done.notify_all();
@@ -317,6 +346,7 @@ lpa_status serve_init(lpa_ctx* ctx) {
   Scheduler* s = new (std::nothrow) Scheduler();
   if (!s) return set_error(LPA_ERR_OOM, "host allocation failed");
   s->ctx = ctx;
+  if (const char* fa = std::getenv("LPA_TEST_FAIL_AFTER")) s->fail_after = std::strtoll(fa, nullptr, 10);
   hipError_t e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
   for (int i = 0; e == hipSuccess && i < 2; ++i) e = hipStreamCreateWithFlags(&s->compute[i], hipStreamNonBlocking);
   const size_t sb = sizeof(uint64_t) * 2 * Scheduler::kMaxBatch;

@@ -129,6 +129,57 @@ def test_batch_graph_reused_across_lds_sizes(torch_mod):
     ctx.close()
 
 
+def test_injected_failure_fails_pending_and_context_recreates(torch_mod, monkeypatch):
+    """LPA_TEST_FAIL_AFTER=2 (the serving loop's second batch launch fails
+    from the host, no GPU work enqueued): the first frame completes, every
+    later ticket ends with LPA_ERR_DEVICE, submissions are refused, and a new
+    context on the device reconstructs as before."""
+    torch = torch_mod
+    from paper_1308_4908_amd import Context, LpaError, Rig, lpa
+
+    frames = make_frames(3, seed0=4400)
+    sensors, raws, p = frames[0]
+    monkeypatch.setenv("LPA_TEST_FAIL_AFTER", "2")
+    ctx = Context(0)
+    monkeypatch.delenv("LPA_TEST_FAIL_AFTER")
+    rig = Rig(ctx, sensors)
+    dev = [torch.from_numpy(r).cuda() for r in raws]
+    ref = alone(torch, ctx, rig, dev, p)
+    outs = [torch.full((p["out_h"], p["out_w"], 3), -1.0, device="cuda") for _ in range(5)]
+    torch.cuda.synchronize()
+    _say("[gpu] injected serving failure: first batch")
+    t0 = rig.submit(dev, p, outs[0])
+    ctx.drain()
+    r0 = ctx.poll(t0)
+    assert r0.status == lpa.OK
+    assert np.array_equal(outs[0].cpu().numpy(), ref[0], equal_nan=True)
+    _say("[gpu] injected serving failure: later batches")
+    # the loop may fail the context while these are submitted: then the
+    # submission itself is refused with the same status
+    tickets = []
+    for o in outs[1:]:
+        try:
+            tickets.append(rig.submit(dev, p, o))
+        except LpaError as e:
+            assert e.status == lpa.ERR_DEVICE
+    assert tickets
+    with pytest.raises(LpaError):
+        ctx.drain()
+    for t in tickets:
+        assert ctx.poll(t).status == lpa.ERR_DEVICE
+    with pytest.raises(LpaError) as e:
+        rig.submit(dev, p, outs[1])
+    assert e.value.status == lpa.ERR_DEVICE
+    assert "LPA_TEST_FAIL_AFTER" in str(e.value)
+    ctx.close()
+    _say("[gpu] injected serving failure: new context")
+    ctx2 = Context(0)
+    rig2 = Rig(ctx2, sensors)
+    assert np.array_equal(alone(torch, ctx2, rig2, dev, p)[0], ref[0], equal_nan=True)
+    rig2.close()
+    ctx2.close()
+
+
 def _serve(torch, ctx, items, host_pinned=True):
     """Submit items = [(rig, raws_np, params)] as fast as possible; returns outputs and results."""
     outs, tickets, hosts = [], [], []
