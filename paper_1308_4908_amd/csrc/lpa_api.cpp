@@ -392,6 +392,29 @@ lpa_status build_launch(const lpa_rig* rig, const Resolved& R, const lpa_frame* 
                        lpa_k_fit_max_lds_bytes());
   }
   K->lds_floats2 = lds;
+  // FP64 refit blocks: the largest whose sensors' raw footprints (the block's
+  // corners widened as the kernel widens them) fit the refit launch's LDS
+  static const int kRefitBlocks[][2] = {{32, 32}, {32, 16}, {16, 16}, {16, 8}, {8, 8}, {8, 4}, {4, 4}, {2, 2}};
+  const int64_t es = frame->dtype == LPA_DTYPE_F32 ? 4 : 2;
+  K->refit_bw = K->refit_bh = 0;
+  for (const auto& b : kRefitBlocks) {
+    int64_t n = 0;
+    for (int s = 0; s < rig->n; ++s) {
+      const SensorK& S = K->s[s];
+      const double L00 = S.inv[0] * O[0] + S.inv[1] * O[3], L01 = S.inv[0] * O[1] + S.inv[1] * O[4];
+      const double L10 = S.inv[3] * O[0] + S.inv[4] * O[3], L11 = S.inv[3] * O[1] + S.inv[4] * O[4];
+      const double ex = std::fabs(L00) * (b[0] - 1) + std::fabs(L01) * (b[1] - 1);
+      const double ey = std::fabs(L10) * (b[0] - 1) + std::fabs(L11) * (b[1] - 1);
+      n += (int64_t)(std::ceil(ex + 2 * S.wmax[0]) + 8) * (int64_t)(std::ceil(ey + 2 * S.wmax[1]) + 8);
+    }
+    if (n * es <= lpa_k_refit_max_lds_bytes()) {
+      K->refit_bw = b[0];
+      K->refit_bh = b[1];
+      K->refit_lds = (int32_t)n;
+      break;
+    }
+  }
+  if (!K->refit_bw) return set_error(LPA_ERR_UNSUPPORTED, "the FP64 refit cannot stage these windows");
   return LPA_OK;
 }
 

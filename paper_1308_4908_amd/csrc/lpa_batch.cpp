@@ -106,8 +106,8 @@ lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_f
   return LPA_OK;
 }
 
-lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, int block, int lds, int grid,
-                        int64_t total, hipStream_t stream);
+lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, int block, int lds,
+                        int refit_lds, int grid, int64_t total, hipStream_t stream);
 
 static void slot_release(BatchSlot& sl) {
   if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
@@ -125,13 +125,14 @@ lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks_in, int src
                         bool charge) {
   std::vector<LaunchK> ks = ks_in;
   int block = ks[0].tile_w * ks[0].tile_h;
-  int lds = 0;
+  int lds = 0, refit_lds = 0;
   int64_t total = 0;
   for (const LaunchK& K : ks) {
     if (K.tile_w * K.tile_h != block) return set_error(LPA_ERR_INTERNAL, "batch tiles differ in lane count");
     for (int s = 0; s < K.n_sensors; ++s)
       if (!K.s[s].raw) return set_error(LPA_ERR_INTERNAL, "batch frame without raw planes");
     lds = std::max(lds, K.lds_floats2);
+    refit_lds = std::max(refit_lds, K.refit_lds * (K.s[0].raw_f32 ? 4 : 2));
     total += (int64_t)K.tiles_x * K.tiles_y;
   }
   if (total > (int64_t)INT32_MAX) return set_error(LPA_ERR_UNSUPPORTED, "batch exceeds 2^31 tiles");
@@ -170,7 +171,7 @@ lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks_in, int src
       at += (size_t)K.out_w * K.out_h * 3;
     }
   }
-  lpa_status st = launch_table(ctx, ks, src_kind, block, lds, grid, total, stream);
+  lpa_status st = launch_table(ctx, ks, src_kind, block, lds, refit_lds, grid, total, stream);
   free_async(ctx, rbuf, rbytes, stream, charge);
   free_async(ctx, cbuf, cbytes, stream, charge);
   return st;
@@ -179,8 +180,8 @@ lpa_status launch_batch(lpa_ctx* ctx, const std::vector<LaunchK>& ks_in, int src
 // Copy the table into a slot and replay (or build) its graph: the table copy,
 // the queue reset, the persistent kernel, the FP64 refit and the count
 // reduction.
-lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, int block, int lds, int grid,
-                        int64_t total, hipStream_t stream) {
+lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_kind, int block, int lds,
+                        int refit_lds, int grid, int64_t total, hipStream_t stream) {
   const int n = (int)ks.size();
 
   std::lock_guard<std::mutex> g(ctx->batch_mu);
@@ -217,7 +218,8 @@ lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
   // The graph depends on the source kind, block, grid and capacity; a batch
   // whose frames need another LDS size updates the two kernel nodes of the
   // instantiated graph.
-  const int64_t sig[4] = {src_kind, block, grid, sl.cap};
+  const int raw_f32 = ks[0].s[0].raw_f32;  // one dtype per batch
+  const int64_t sig[5] = {src_kind, block, grid, sl.cap, raw_f32};
   char* d = static_cast<char*>(sl.d_buf);
   const auto* d_hdr = reinterpret_cast<const BatchHeader*>(d);
   const auto* d_frames = reinterpret_cast<const LaunchK*>(d + L.frames_off);
@@ -225,12 +227,14 @@ lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
   auto* d_queue = reinterpret_cast<int32_t*>(d + L.queue_off);
   const int refit_grid = ctx->n_cu * 8;
   bool rebuild = !sl.exec || std::memcmp(sig, sl.sig, sizeof(sig)) != 0;
-  if (!rebuild && sl.lds != lds) {
+  if (!rebuild && (sl.lds != lds || sl.refit_lds != refit_lds)) {
     // another LDS size: update the two nodes in place; a runtime that refuses
     // the update gets a new graph instead
     if (lpa_k_batch_graph_set_lds(sl.exec, sl.fit_node, sl.refit_node, d_hdr, d_frames, d_first, d_queue, src_kind,
-                                  block, lds, grid, refit_grid) == 0)
+                                  block, lds, refit_lds, grid, refit_grid, raw_f32) == 0) {
       sl.lds = lds;
+      sl.refit_lds = refit_lds;
+    }
     else {
       (void)hipGetLastError();
       rebuild = true;
@@ -242,7 +246,7 @@ lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
     sl.exec = nullptr;
     sl.graph = nullptr;
     if (lpa_k_batch_graph(&sl.graph, &sl.fit_node, &sl.refit_node, d, h, L.copy_bytes, d_hdr, d_frames, d_first,
-                          d_queue, src_kind, block, lds, grid, refit_grid, sl.cap) != 0)
+                          d_queue, src_kind, block, lds, refit_lds, grid, refit_grid, sl.cap, raw_f32) != 0)
       return device_error(ctx, hipGetLastError(), "batch graph");
     e = hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -251,6 +255,7 @@ lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
     }
     std::memcpy(sl.sig, sig, sizeof(sig));
     sl.lds = lds;
+    sl.refit_lds = refit_lds;
   }
   if ((e = hipGraphLaunch(sl.exec, stream)) != hipSuccess) return device_error(ctx, e, "graph launch");
   if ((e = hipEventRecord(sl.done, stream)) != hipSuccess) return device_error(ctx, e, "event record");

@@ -104,8 +104,9 @@ struct BatchSlot {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;     // kept with exec: its node handles name the nodes to update
   hipGraphNode_t fit_node = nullptr, refit_node = nullptr;
-  int64_t sig[4] = {0, 0, 0, 0};  // source kind, block, grid, capacity
+  int64_t sig[5] = {0, 0, 0, 0, 0};  // source kind, block, grid, capacity, raw float DN
   int lds = 0;                    // dynamic LDS of the fit node (float2 elements)
+  int refit_lds = 0;              // dynamic LDS of the refit node (bytes)
 };
 
 // Byte layout of a batch table of capacity cap.

@@ -120,7 +120,7 @@ struct LaunchK {
   // risk_max * max(|C0|, value_floor) (risk_max = +inf: never).
   float risk_max;
   float value_floor;        // one DN of the most exposed sensor, in radiance units
-  int32_t pad2_;
+  int32_t refit_lds;
   // optional per-tile counts (2 x uint32 per tile: outputs whose value came
   // from an FP64 solve, outputs with no valid fit), indexed by the frame's
   // tile number; null: not counted
@@ -131,6 +131,9 @@ struct LaunchK {
   // the refit launch (null: no refit)
   uint8_t* refit_map;
   int64_t refit_pitch;      // bytes
+  // FP64 refit blocks: refit_bw x refit_bh output pixels per workgroup (at
+  // most 32 x 32), staging refit_lds raw DN (the sensors' block footprints)
+  int32_t refit_bw, refit_bh;
   float* rgb;
   int64_t rgb_pitch;        // bytes
   uint8_t* map;
@@ -213,12 +216,12 @@ int lpa_k_fit_stencil(const lpa::LaunchK* k, void* stream);
 // Fit with per-pixel steered windows read from K.steer.
 int lpa_k_fit_steered(const lpa::LaunchK* k, void* stream);
 // FP64 refit of the outputs a fit launch marked in K.refit_map (one launch
-// over the frame's tiles, after the fit on the same stream).
+// over the frame's refit blocks, after the fit on the same stream).
 int lpa_k_refit(const lpa::LaunchK* k, void* stream);
 // The same for a batch table (after the persistent fit; grid workgroups loop
-// over the batch's tiles).
+// over the batch's refit blocks; lds_bytes covers every frame's refit_lds).
 int lpa_k_refit_batch(const lpa::BatchHeader* hdr, const lpa::LaunchK* frames, const int64_t* first_tile,
-                      int32_t grid, int32_t lds_floats2, void* stream);
+                      int32_t grid, int32_t lds_bytes, int32_t raw_f32, void* stream);
 // The graph of one batch, built node by node: copy of the table (copy_bytes
 // from pinned h_table to d_table, which holds d_hdr / d_frames / d_first),
 // queue reset, persistent fit (grid x block, lds_floats2 float2 of LDS), FP64
@@ -229,11 +232,14 @@ int lpa_k_refit_batch(const lpa::BatchHeader* hdr, const lpa::LaunchK* frames, c
 int lpa_k_batch_graph(hipGraph_t* out, hipGraphNode_t* fit_node, hipGraphNode_t* refit_node, void* d_table,
                       const void* h_table, size_t copy_bytes, const lpa::BatchHeader* d_hdr,
                       const lpa::LaunchK* d_frames, const int64_t* d_first, int32_t* d_queue, int32_t src_kind,
-                      int32_t block, int32_t lds_floats2, int32_t grid, int32_t refit_grid, int32_t cap);
+                      int32_t block, int32_t lds_floats2, int32_t refit_lds_bytes, int32_t grid, int32_t refit_grid,
+                      int32_t cap, int32_t raw_f32);
 int lpa_k_batch_graph_set_lds(hipGraphExec_t exec, hipGraphNode_t fit_node, hipGraphNode_t refit_node,
                               const lpa::BatchHeader* d_hdr, const lpa::LaunchK* d_frames, const int64_t* d_first,
-                              int32_t* d_queue, int32_t src_kind, int32_t block, int32_t lds_floats2, int32_t grid,
-                              int32_t refit_grid);
+                              int32_t* d_queue, int32_t src_kind, int32_t block, int32_t lds_floats2,
+                              int32_t refit_lds_bytes, int32_t grid, int32_t refit_grid, int32_t raw_f32);
+// Dynamic LDS a refit launch may take (bytes).
+int lpa_k_refit_max_lds_bytes(void);
 // Zero n ints with a small kernel (graph-safe replacement for a memset).
 int lpa_k_zero_i32(int32_t* p, int32_t n, void* stream);
 // Sum a frame's per-tile counts (n_tiles pairs) into out[0], out[1].

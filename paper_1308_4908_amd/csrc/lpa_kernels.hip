@@ -897,8 +897,8 @@ __device__ __forceinline__ void acc64_d(Acc64<ORDER>& a, double x, double y, dou
 // r' (the ellipse d^T C d < r'^2, whose half-width along a sensor axis with
 // inverse-map row a is r' sqrt(a^T C^-1 a)).  One lane per output.
 template <int ORDER, bool STEER, typename RawT>
-__device__ double refit_one(const LaunchK& K, const RawT* raw, const Region* regs, int u, int v, int c, int o,
-                            int m) {
+__device__ double refit_one(const LaunchK& K, const RawT* raw, const Region* regs, const int* offs, int u, int v,
+                            int c, int o, int m) {
   const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
   const double Yj = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
   const int cls = (c == 1) ? 1 : 0;
@@ -922,7 +922,7 @@ __device__ double refit_one(const LaunchK& K, const RawT* raw, const Region* reg
   for (int s = 0; s < K.n_sensors; ++s) {
     const SensorK& S = K.s[s];
     const Region R = regs[s];
-    const RawT* plane = raw + S.lds_off;
+    const RawT* plane = raw + offs[s];
     // the frame's temporal factor exp(-t^2 / h_t) (temporal LPA; 1 at t = 0,
     // 0 where the FP32 pass has it 0: h_t = 0)
     const double kt =
@@ -933,6 +933,12 @@ __device__ double refit_one(const LaunchK& K, const RawT* raw, const Region* reg
     const double wx = r * sqrt(ax * ax * ixx + 2.0 * ax * ay * ixy + ay * ay * iyy) * (1.0 + 1e-12);
     const double wy = r * sqrt(bx * bx * ixx + 2.0 * bx * by * ixy + by * by * iyy) * (1.0 + 1e-12);
     const int nx = max(1, (int)ceil(wx - 1e-9)), ny = max(1, (int)ceil(wy - 1e-9));
+    // one step along a sub-lattice row (+2 sensor px in x), in the reference
+    // plane; d2 along the row is quadratic in the step index, so the window's
+    // exp(-d2 / h) is a product recurrence: e_{i+1} = e_i q_i, q_{i+1} = q_i cq
+    const double sx = 2.0 * S.fwd[0], sy = 2.0 * S.fwd[3];
+    const double qs = cxx * sx * sx + 2.0 * cxy * sx * sy + cyy * sy * sy;  // second difference / 2
+    const double cq = exp_neg64(2.0 * qs * ih);
     for (int q = 0; q < S.sub_n[c]; ++q) {
       const int ox = S.sub_ox[c][q], oy = S.sub_oy[c][q];
       const int xb = ox + 2 * (int)ceil((px - wx - ox) * 0.5);
@@ -941,7 +947,14 @@ __device__ double refit_one(const LaunchK& K, const RawT* raw, const Region* reg
         const int y = yb + 2 * j;
         if (y < 0 || y >= S.height) continue;
         const RawT* row = plane + (y - R.y0) * R.w - R.x0;
-        for (int i = 0; i < nx; ++i) {
+        // the row's first point: its window exponent and the first step's factor
+        const double dX0 = S.fwd[0] * xb + S.fwd[1] * y + S.fwd[2] - Xj;
+        const double dY0 = S.fwd[3] * xb + S.fwd[4] * y + S.fwd[5] - Yj;
+        const double d20 = cxx * dX0 * dX0 + 2.0 * cxy * dX0 * dY0 + cyy * dY0 * dY0;
+        const double lin = 2.0 * (cxx * dX0 * sx + cxy * (dX0 * sy + dY0 * sx) + cyy * dY0 * sy);
+        double e = exp_neg64(d20 * ih);
+        double qf = exp_neg64((lin + qs) * ih);
+        for (int i = 0; i < nx; ++i, e *= qf, qf *= cq) {
           const int x = xb + 2 * i;
           if (x < 0 || x >= S.width) continue;
           const double dX = S.fwd[0] * x + S.fwd[1] * y + S.fwd[2] - Xj;
@@ -950,7 +963,7 @@ __device__ double refit_one(const LaunchK& K, const RawT* raw, const Region* reg
           if (!(d2 < r2)) continue;
           double f, iv;
           if (decode64(S, (int64_t)y * S.width + x, (double)row[x], f, iv))
-            acc64_d<ORDER>(a, dX, dY, f, (exp_neg64(d2 * ih) - ee) * kt * iv);
+            acc64_d<ORDER>(a, dX, dY, f, (e - ee) * kt * iv);
         }
       }
     }
@@ -971,56 +984,95 @@ __device__ double refit_one(const LaunchK& K, const RawT* raw, const Region* reg
 // (channel, radius) -- a counting sort, so the lanes of a wave mostly walk
 // boxes of one shape -- then each lane of the workgroup takes one.
 constexpr int kRefitClasses = 3 * kMaxScales;
-constexpr int kRefitBlock = 64;  // one wave per tile
+constexpr int kRefitThreads = 256;  // one workgroup per output block
+constexpr int kRefitMaxOut = 32 * 32 * 3;
 
+// Sensor footprint staged for the output block at (u0, v0) of cw x ch
+// pixels: the block corners' sensor positions widened by the largest box
+// half-width and a margin (the host bounds its size by the same rule).
+__device__ __forceinline__ Region block_region(const LaunchK& K, const SensorK& S, int u0, int v0, int cw, int ch) {
+  double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double u = u0 + ((c & 1) ? cw - 1 : 0);
+    const double v = v0 + ((c & 2) ? ch - 1 : 0);
+    const double X = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
+    const double Y = K.out_affine[3] * u + K.out_affine[4] * v + K.out_affine[5];
+    const double px = S.inv[0] * X + S.inv[1] * Y + S.inv[2];
+    const double py = S.inv[3] * X + S.inv[4] * Y + S.inv[5];
+    mnx = fmin(mnx, px);
+    mxx = fmax(mxx, px);
+    mny = fmin(mny, py);
+    mxy = fmax(mxy, py);
+  }
+  Region r;
+  r.x0 = (int)floor(mnx - S.wmax[0]) - 1;
+  r.y0 = (int)floor(mny - S.wmax[1]) - 1;
+  r.w = (int)ceil(mxx + S.wmax[0]) + 3 - r.x0 + 1;
+  r.h = (int)ceil(mxy + S.wmax[1]) + 3 - r.y0 + 1;
+  return r;
+}
+
+// The FP64 refit of the marked outputs of one output block (K.refit_bw x
+// K.refit_bh pixels, row-major block number b): the marks are gathered in LDS
+// ordered by (channel, radius) -- a counting sort, so the lanes of a wave
+// mostly walk boxes of one shape -- the block's raw samples are staged, and
+// each lane refits one output.  Every output is computed by one lane from
+// the same samples in the same order whatever the block, tile or batch.
 template <int ORDER, bool STEER, typename RawT>
-__device__ __forceinline__ void refit_tile(const LaunchK& K, int tile, uint16_t* list, int* count, RawT* raw,
-                                           Region* regs) {
-  const int u0 = (tile % K.tiles_x) * K.tile_w, v0 = (tile / K.tiles_x) * K.tile_h;
-  const int n_out = K.tile_w * K.tile_h * 3;
-  for (int k = threadIdx.x; k <= kRefitClasses; k += blockDim.x) count[k] = 0;
-  // each lane holds the codes of outputs t = threadIdx.x + k * kRefitBlock
-  constexpr int kCodes = 768 / kRefitBlock;
+__device__ __forceinline__ void refit_block(const LaunchK& K, int b, uint16_t* list, int* count, RawT* raw,
+                                            Region* regs, int* offs) {
+  const int bx = (K.out_w + K.refit_bw - 1) / K.refit_bw;
+  const int u0 = (b % bx) * K.refit_bw, v0 = (b / bx) * K.refit_bh;
+  const int cw = min(K.refit_bw, K.out_w - u0), ch = min(K.refit_bh, K.out_h - v0);
+  const int n_out = cw * ch * 3;
+  const int tid = threadIdx.x;
+  for (int k = tid; k <= kRefitClasses; k += kRefitThreads) count[k] = 0;
+  __syncthreads();
+  constexpr int kCodes = kRefitMaxOut / kRefitThreads;
   uint8_t codes[kCodes];
 #pragma unroll
   for (int k = 0; k < kCodes; ++k) {
-    const int t = threadIdx.x + k * kRefitBlock;
+    const int t = tid + k * kRefitThreads;
     const int p = t / 3, c = t - 3 * p;
-    const int u = u0 + p % K.tile_w, v = v0 + p / K.tile_w;
-    codes[k] = (t < n_out && u < K.out_w && v < K.out_h) ? K.refit_map[(int64_t)v * K.refit_pitch + 3 * u + c] : 0;
+    codes[k] = t < n_out ? K.refit_map[(int64_t)(v0 + p / cw) * K.refit_pitch + 3 * (u0 + p % cw) + c] : 0;
+    if (codes[k] & 0x80) atomicAdd(&count[1 + c * kMaxScales + (codes[k] & 7)], 1);
   }
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kCodes; ++k) {
-    const int t = threadIdx.x + k * kRefitBlock;
-    if (codes[k] & 0x80) atomicAdd(&count[1 + (t % 3) * kMaxScales + (codes[k] & 7)], 1);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0)
+  if (tid == 0)
     for (int k = 1; k <= kRefitClasses; ++k) count[k] += count[k - 1];  // count[k]: start of class k
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kCodes; ++k) {
-    const int t = threadIdx.x + k * kRefitBlock;
+    const int t = tid + k * kRefitThreads;
     if (codes[k] & 0x80) list[atomicAdd(&count[(t % 3) * kMaxScales + (codes[k] & 7)], 1)] = (uint16_t)t;
   }
   __syncthreads();
   const int n = count[kRefitClasses - 1];
   if (n == 0) return;  // workgroup-uniform
-  // the tile's raw samples (the fit's regions, which hold every box), read
-  // kStageRun per lane at a time so that their loads are in flight together
-  constexpr int kStageRun = 8;
+  if (tid == 0) {
+    int off = 0;
+    for (int s = 0; s < K.n_sensors; ++s) {
+      const Region r = block_region(K, K.s[s], u0, v0, cw, ch);
+      regs[s] = r;
+      offs[s] = off;
+      off += r.w * r.h;
+    }
+  }
+  __syncthreads();
+  // the block's raw samples, kStageRun per lane at a time so that their loads
+  // are in flight together
+  constexpr int kStageRun = 4;
   for (int s = 0; s < K.n_sensors; ++s) {
     const SensorK& S = K.s[s];
-    const Region r = tile_region(K, S, u0, v0);
-    if (threadIdx.x == 0) regs[s] = r;
-    RawT* dst = raw + S.lds_off;
+    const Region r = regs[s];
+    RawT* dst = raw + offs[s];
     const int total = r.w * r.h;
-    for (int e0 = threadIdx.x; e0 < total; e0 += kStageRun * kRefitBlock) {
+    for (int e0 = tid; e0 < total; e0 += kStageRun * kRefitThreads) {
       RawT val[kStageRun];
 #pragma unroll
       for (int k = 0; k < kStageRun; ++k) {
-        const int e = e0 + k * kRefitBlock;
+        const int e = e0 + k * kRefitThreads;
         const int row = e / r.w, col = e - row * r.w;
         const int x = r.x0 + col, y = r.y0 + row;
         val[k] = RawT(0);
@@ -1029,66 +1081,68 @@ __device__ __forceinline__ void refit_tile(const LaunchK& K, int tile, uint16_t*
       }
 #pragma unroll
       for (int k = 0; k < kStageRun; ++k)
-        if (e0 + k * kRefitBlock < total) dst[e0 + k * kRefitBlock] = val[k];
+        if (e0 + k * kRefitThreads < total) dst[e0 + k * kRefitThreads] = val[k];
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  for (int i = tid; i < n; i += kRefitThreads) {
     const int t = list[i];
     const int p = t / 3, c = t - 3 * p;
-    const int u = u0 + p % K.tile_w, v = v0 + p / K.tile_w;
+    const int u = u0 + p % cw, v = v0 + p / cw;
     const int code = K.refit_map[(int64_t)v * K.refit_pitch + 3 * u + c];
-    const double y = refit_one<ORDER, STEER>(K, raw, regs, u, v, c, (code >> 4) & 3, code & 7);
+    const double y = refit_one<ORDER, STEER>(K, raw, regs, offs, u, v, c, (code >> 4) & 3, code & 7);
     float* orow = reinterpret_cast<float*>(reinterpret_cast<char*>(K.rgb) + (int64_t)v * K.rgb_pitch);
     orow[3 * u + c] = (float)y;
   }
   __syncthreads();
 }
 
-// One workgroup per tile; dynamic LDS: the raw samples of the tile's regions
-// (K.lds_floats2 elements of RawT: uint16 frames as uint16, float DN as float).
+// One workgroup per output block; dynamic LDS: the raw samples of the block's
+// footprints (K.refit_lds elements of RawT: uint16 frames as uint16, float DN
+// as float).
 template <int ORDER, bool STEER, typename RawT>
-__global__ void __launch_bounds__(kRefitBlock) refit_kernel(const LaunchK K) {
+__global__ void __launch_bounds__(kRefitThreads) refit_kernel(const LaunchK K) {
   extern __shared__ float2 lds[];
-  __shared__ uint16_t list[768];
+  __shared__ uint16_t list[kRefitMaxOut];
   __shared__ int count[kRefitClasses + 1];
   __shared__ Region regs[kMaxSensors];
-  refit_tile<ORDER, STEER, RawT>(K, xcd_tile(blockIdx.x, gridDim.x), list, count, reinterpret_cast<RawT*>(lds),
-                                 regs);
+  __shared__ int offs[kMaxSensors];
+  refit_block<ORDER, STEER, RawT>(K, blockIdx.x, list, count, reinterpret_cast<RawT*>(lds), regs, offs);
 }
 
-// Batch form: workgroups take tiles t = blockIdx.x, blockIdx.x + gridDim.x, ...
+// Batch form: the batch's blocks, frame after frame, are numbered 0, 1, ...;
+// workgroup w takes blocks w, w + gridDim.x, ... (frames without refits have
+// no blocks).
 template <typename RawT>
-__device__ __forceinline__ void refit_batch_frame(const LaunchK& K, int local, uint16_t* list, int* count,
-                                                  RawT* raw, Region* regs) {
+__device__ __forceinline__ void refit_batch_frame(const LaunchK& K, int b, uint16_t* list, int* count, RawT* raw,
+                                                  Region* regs, int* offs) {
   switch (K.order) {
-    case 0: refit_tile<0, false, RawT>(K, local, list, count, raw, regs); break;
-    case 1: refit_tile<1, false, RawT>(K, local, list, count, raw, regs); break;
-    default: refit_tile<2, false, RawT>(K, local, list, count, raw, regs); break;
+    case 0: refit_block<0, false, RawT>(K, b, list, count, raw, regs, offs); break;
+    case 1: refit_block<1, false, RawT>(K, b, list, count, raw, regs, offs); break;
+    default: refit_block<2, false, RawT>(K, b, list, count, raw, regs, offs); break;
   }
 }
 
-__global__ void __launch_bounds__(kRefitBlock) refit_batch_kernel(const BatchHeader* __restrict__ hdr,
-                                                                  const LaunchK* __restrict__ frames,
-                                                                  const int64_t* __restrict__ first_tile) {
+// (all frames of a batch share the raw element type RawT)
+template <typename RawT>
+__global__ void __launch_bounds__(kRefitThreads) refit_batch_kernel(const BatchHeader* __restrict__ hdr,
+                                                                    const LaunchK* __restrict__ frames,
+                                                                    const int64_t* __restrict__ first_tile) {
+  (void)first_tile;
   extern __shared__ float2 lds[];
-  __shared__ uint16_t list[768];
+  __shared__ uint16_t list[kRefitMaxOut];
   __shared__ int count[kRefitClasses + 1];
   __shared__ Region regs[kMaxSensors];
+  __shared__ int offs[kMaxSensors];
   const int n_frames = hdr->n_frames;
-  const int64_t total = hdr->total_tiles;
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    int lo = 0, hi = n_frames - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (first_tile[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    const int f = __builtin_amdgcn_readfirstlane(lo);
+  int64_t g = blockIdx.x, base = 0;
+  for (int f = 0; f < n_frames; ++f) {
     const LaunchK& K = frames[f];
     if (!K.refit_map) continue;
-    const int local = (int)(t - first_tile[f]);
-    if (K.s[0].raw_f32) refit_batch_frame<float>(K, local, list, count, reinterpret_cast<float*>(lds), regs);
-    else refit_batch_frame<uint16_t>(K, local, list, count, reinterpret_cast<uint16_t*>(lds), regs);
+    const int64_t nb = (int64_t)((K.out_w + K.refit_bw - 1) / K.refit_bw) * ((K.out_h + K.refit_bh - 1) / K.refit_bh);
+    for (; g < base + nb; g += gridDim.x)
+      refit_batch_frame<RawT>(K, (int)(g - base), list, count, reinterpret_cast<RawT*>(lds), regs, offs);
+    base += nb;
   }
 }
 
@@ -1997,12 +2051,15 @@ extern "C" int lpa_k_fit_batch(const BatchHeader* d_hdr, const LaunchK* d_frames
 
 extern "C" int lpa_k_refit(const LaunchK* k, void* stream) {
   const LaunchK& K = *k;
-  if (!K.refit_map || !raw_bound(K) || K.tile_w * K.tile_h > 256) return -1;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const dim3 grid(K.tiles_x * K.tiles_y), block(kRefitBlock);
-  const bool steer = K.steer != nullptr;
   const bool f32 = K.s[0].raw_f32 != 0;
-  const size_t lds = (size_t)K.lds_floats2 * (f32 ? 4 : 2);
+  const size_t lds = (size_t)K.refit_lds * (f32 ? 4 : 2);
+  if (!K.refit_map || !raw_bound(K) || K.refit_bw < 1 || K.refit_bh < 1 || K.refit_bw * K.refit_bh * 3 > kRefitMaxOut ||
+      lds > (size_t)lpa_k_refit_max_lds_bytes())
+    return -1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid(((K.out_w + K.refit_bw - 1) / K.refit_bw) * ((K.out_h + K.refit_bh - 1) / K.refit_bh)),
+      block(kRefitThreads);
+  const bool steer = K.steer != nullptr;
 #define LPA_REFIT(O, ST)                                                          \
   (f32 ? (refit_kernel<O, ST, float><<<grid, block, lds, st>>>(K), 0)          \
        : (refit_kernel<O, ST, uint16_t><<<grid, block, lds, st>>>(K), 0))
@@ -2020,10 +2077,18 @@ extern "C" int lpa_k_refit(const LaunchK* k, void* stream) {
 }
 
 extern "C" int lpa_k_refit_batch(const BatchHeader* hdr, const LaunchK* frames, const int64_t* first_tile,
-                                 int32_t grid, int32_t lds_floats2, void* stream) {
-  const size_t lds = (size_t)lds_floats2 * 4;
-  refit_batch_kernel<<<grid, kRefitBlock, lds, static_cast<hipStream_t>(stream)>>>(hdr, frames, first_tile);
+                                 int32_t grid, int32_t lds_bytes, int32_t raw_f32, void* stream) {
+  if (lds_bytes > lpa_k_refit_max_lds_bytes()) return -1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (raw_f32) refit_batch_kernel<float><<<grid, kRefitThreads, (size_t)lds_bytes, st>>>(hdr, frames, first_tile);
+  else refit_batch_kernel<uint16_t><<<grid, kRefitThreads, (size_t)lds_bytes, st>>>(hdr, frames, first_tile);
   return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// Dynamic LDS a refit launch may take: 64 KiB less its static arrays.
+extern "C" int lpa_k_refit_max_lds_bytes(void) {
+  return 64 * 1024 - (int)(sizeof(uint16_t) * kRefitMaxOut + sizeof(int) * (kRefitClasses + 1) +
+                           sizeof(Region) * kMaxSensors + sizeof(int) * kMaxSensors) - 256;
 }
 
 namespace {
@@ -2124,12 +2189,14 @@ bool batch_fit_params(BatchNodeArgs& a, int32_t src_kind, int32_t block, int32_t
   return true;
 }
 
-void batch_refit_params(BatchNodeArgs& a, int32_t lds_floats2, int32_t refit_grid, hipKernelNodeParams* p) {
+void batch_refit_params(BatchNodeArgs& a, int32_t refit_lds_bytes, int32_t refit_grid, int32_t raw_f32,
+                        hipKernelNodeParams* p) {
   *p = hipKernelNodeParams{};
-  p->func = reinterpret_cast<void*>(&refit_batch_kernel);
+  p->func = raw_f32 ? reinterpret_cast<void*>(&refit_batch_kernel<float>)
+                    : reinterpret_cast<void*>(&refit_batch_kernel<uint16_t>);
   p->gridDim = dim3(refit_grid);
-  p->blockDim = dim3(kRefitBlock);
-  p->sharedMemBytes = (unsigned)((size_t)lds_floats2 * 4);
+  p->blockDim = dim3(kRefitThreads);
+  p->sharedMemBytes = (unsigned)refit_lds_bytes;
   p->kernelParams = a.refit;
 }
 }  // namespace
@@ -2137,7 +2204,8 @@ void batch_refit_params(BatchNodeArgs& a, int32_t lds_floats2, int32_t refit_gri
 extern "C" int lpa_k_batch_graph(hipGraph_t* out, hipGraphNode_t* fit_node, hipGraphNode_t* refit_node,
                                  void* d_table, const void* h_table, size_t copy_bytes, const BatchHeader* d_hdr,
                                  const LaunchK* d_frames, const int64_t* d_first, int32_t* d_queue, int32_t src_kind,
-                                 int32_t block, int32_t lds_floats2, int32_t grid, int32_t refit_grid, int32_t cap) {
+                                 int32_t block, int32_t lds_floats2, int32_t refit_lds_bytes, int32_t grid,
+                                 int32_t refit_grid, int32_t cap, int32_t raw_f32) {
   *out = nullptr;
   hipGraph_t g = nullptr;
   if (hipGraphCreate(&g, 0) != hipSuccess) return -2;
@@ -2171,7 +2239,7 @@ extern "C" int lpa_k_batch_graph(hipGraph_t* out, hipGraphNode_t* fit_node, hipG
   BatchNodeArgs args(d_hdr, d_frames, d_first, d_queue);
   if (e == hipSuccess && !batch_fit_params(args, src_kind, block, lds_floats2, grid, &p)) e = hipErrorInvalidValue;
   if (e == hipSuccess) e = hipGraphAddKernelNode(&n_fit, g, &n_zero, 1, &p);
-  batch_refit_params(args, lds_floats2, refit_grid, &p);
+  batch_refit_params(args, refit_lds_bytes, refit_grid, raw_f32, &p);
   if (e == hipSuccess) e = hipGraphAddKernelNode(&n_refit, g, &n_fit, 1, &p);
   void* stats_args[] = {&d_hdr, &d_frames};
   p = hipKernelNodeParams{};
@@ -2194,12 +2262,12 @@ extern "C" int lpa_k_batch_graph(hipGraph_t* out, hipGraphNode_t* fit_node, hipG
 extern "C" int lpa_k_batch_graph_set_lds(hipGraphExec_t exec, hipGraphNode_t fit_node, hipGraphNode_t refit_node,
                                          const BatchHeader* d_hdr, const LaunchK* d_frames, const int64_t* d_first,
                                          int32_t* d_queue, int32_t src_kind, int32_t block, int32_t lds_floats2,
-                                         int32_t grid, int32_t refit_grid) {
+                                         int32_t refit_lds_bytes, int32_t grid, int32_t refit_grid, int32_t raw_f32) {
   BatchNodeArgs args(d_hdr, d_frames, d_first, d_queue);
   hipKernelNodeParams p{};
   if (!batch_fit_params(args, src_kind, block, lds_floats2, grid, &p)) return -1;
   if (hipGraphExecKernelNodeSetParams(exec, fit_node, &p) != hipSuccess) return -2;
-  batch_refit_params(args, lds_floats2, refit_grid, &p);
+  batch_refit_params(args, refit_lds_bytes, refit_grid, raw_f32, &p);
   if (hipGraphExecKernelNodeSetParams(exec, refit_node, &p) != hipSuccess) return -2;
   return 0;
 }
