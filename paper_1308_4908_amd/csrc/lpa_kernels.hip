@@ -1107,7 +1107,9 @@ __global__ void __launch_bounds__(kRefitThreads) refit_kernel(const LaunchK K) {
   __shared__ int count[kRefitClasses + 1];
   __shared__ Region regs[kMaxSensors];
   __shared__ int offs[kMaxSensors];
-  refit_block<ORDER, STEER, RawT>(K, blockIdx.x, list, count, reinterpret_cast<RawT*>(lds), regs, offs);
+  // neighbouring blocks on one XCD share their halos in its L2
+  refit_block<ORDER, STEER, RawT>(K, xcd_tile(blockIdx.x, gridDim.x), list, count, reinterpret_cast<RawT*>(lds), regs,
+                                  offs);
 }
 
 // Batch form: the batch's blocks, frame after frame, are numbered 0, 1, ...;
@@ -1135,7 +1137,9 @@ __global__ void __launch_bounds__(kRefitThreads) refit_batch_kernel(const BatchH
   __shared__ Region regs[kMaxSensors];
   __shared__ int offs[kMaxSensors];
   const int n_frames = hdr->n_frames;
-  int64_t g = blockIdx.x, base = 0;
+  // the workgroup's slot: XCD-contiguous (workgroup i runs on XCD i mod 8),
+  // so that neighbouring blocks share their halos in one L2
+  int64_t g = xcd_tile(blockIdx.x, gridDim.x), base = 0;
   for (int f = 0; f < n_frames; ++f) {
     const LaunchK& K = frames[f];
     if (!K.refit_map) continue;
