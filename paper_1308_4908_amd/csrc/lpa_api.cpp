@@ -470,7 +470,7 @@ void free_async(lpa_ctx* ctx, void* p, size_t bytes, hipStream_t st, bool charge
 
 // Pre-pass every sensor into planes; fills srcs/pitches and the allocations.
 lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_t st, void** planes,
-                       size_t* plane_bytes, const void** srcs, int64_t* pitches, bool charge, bool launch) {
+                       size_t* plane_bytes, const void** srcs, int64_t* pitches, bool charge) {
   lpa_ctx* ctx = rig->ctx;
   for (int s = 0; s < rig->n; ++s) {
     const SensorK& S = rig->k[s];
@@ -479,7 +479,7 @@ lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_
     lpa_status rs = alloc_async(ctx, plane_bytes[s], st, &planes[s], charge);
     if (rs != LPA_OK) return rs;
     const float enc = std::ldexp(1.0f, -rig->desc[s].bit_depth);
-    if (launch && lpa_k_prepass(&S, f->dtype == LPA_DTYPE_F32, f->raw[s], f->row_pitch_bytes[s], planes[s], pitch,
+    if (lpa_k_prepass(&S, f->dtype == LPA_DTYPE_F32, f->raw[s], f->row_pitch_bytes[s], planes[s], pitch,
                                 to_f16 ? 1 : 0, enc, st) != 0)
       return device_error(ctx, hipGetLastError(), "pre-pass launch");
     srcs[s] = planes[s];

@@ -86,22 +86,26 @@ lpa_status prepare_frames(lpa_ctx* ctx, int n, lpa_rig* const* rigs, const lpa_f
   }
   *src_kind = sk;
   if (sk == SRC_PLANE_F32 || sk == SRC_PLANE_F16) {
-    for (int i = 0; i < n; ++i) {
-      void* pl[LPA_MAX_SENSORS] = {nullptr};
-      size_t pb[LPA_MAX_SENSORS] = {0};
-      const void* srcs[LPA_MAX_SENSORS];
-      int64_t pitches[LPA_MAX_SENSORS];
-      // the planes only: the batch graph's pre-pass node fills them
-      lpa_status st =
-          run_prepass(rigs[i], &frames[i], sk == SRC_PLANE_F16, stream, pl, pb, srcs, pitches, charge, false);
+    // the planes only, carved from one allocation (one stream-ordered
+    // allocation per batch, not one per sensor): the batch graph's pre-pass
+    // node fills them
+    const int64_t es = sk == SRC_PLANE_F16 ? 2 : 8;
+    size_t bytes = 0;
+    for (int i = 0; i < n; ++i)
       for (int s = 0; s < rigs[i]->n; ++s)
-        if (pl[s]) planes->push_back({pl[s], pb[s]});
-      if (st != LPA_OK) return st;
+        bytes += (size_t)((rigs[i]->k[s].width * es + 255) / 256 * 256) * rigs[i]->k[s].height;
+    void* buf = nullptr;
+    lpa_status st = alloc_async(ctx, bytes, stream, &buf, charge);
+    if (st != LPA_OK) return st;
+    planes->push_back({buf, bytes});
+    size_t at = 0;
+    for (int i = 0; i < n; ++i)
       for (int s = 0; s < rigs[i]->n; ++s) {
-        (*ks)[i].s[s].src = srcs[s];
-        (*ks)[i].s[s].pitch = pitches[s];
+        const int64_t pitch = (rigs[i]->k[s].width * es + 255) / 256 * 256;
+        (*ks)[i].s[s].src = static_cast<char*>(buf) + at;
+        (*ks)[i].s[s].pitch = pitch;
+        at += (size_t)pitch * rigs[i]->k[s].height;
       }
-    }
   }
   return LPA_OK;
 }
@@ -225,15 +229,22 @@ lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
   const auto* d_frames = reinterpret_cast<const LaunchK*>(d + L.frames_off);
   const auto* d_first = reinterpret_cast<const int64_t*>(d + L.first_off);
   auto* d_queue = reinterpret_cast<int32_t*>(d + L.queue_off);
-  const int refit_grid = ctx->n_cu * 8;
+  // the refit takes one workgroup per output block of the frames it covers
+  int64_t refit_blocks = 0;
+  for (const LaunchK& K : ks)
+    if (K.refit_map)
+      refit_blocks += (int64_t)((K.out_w + K.refit_bw - 1) / K.refit_bw) * ((K.out_h + K.refit_bh - 1) / K.refit_bh);
+  if (refit_blocks > (int64_t)INT32_MAX) return set_error(LPA_ERR_UNSUPPORTED, "batch exceeds 2^31 refit blocks");
+  const int refit_grid = (int)std::max<int64_t>(refit_blocks, 1);
   bool rebuild = !sl.exec || std::memcmp(sig, sl.sig, sizeof(sig)) != 0;
-  if (!rebuild && (sl.lds != lds || sl.refit_lds != refit_lds)) {
-    // another LDS size: update the two nodes in place; a runtime that refuses
-    // the update gets a new graph instead
+  if (!rebuild && (sl.lds != lds || sl.refit_lds != refit_lds || sl.refit_grid != refit_grid)) {
+    // another LDS size or refit grid: update the two nodes in place; a
+    // runtime that refuses the update gets a new graph instead
     if (lpa_k_batch_graph_set_lds(sl.exec, sl.fit_node, sl.refit_node, d_hdr, d_frames, d_first, d_queue, src_kind,
                                   block, lds, refit_lds, grid, refit_grid, raw_f32) == 0) {
       sl.lds = lds;
       sl.refit_lds = refit_lds;
+      sl.refit_grid = refit_grid;
     }
     else {
       (void)hipGetLastError();
@@ -256,6 +267,7 @@ lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
     std::memcpy(sl.sig, sig, sizeof(sig));
     sl.lds = lds;
     sl.refit_lds = refit_lds;
+    sl.refit_grid = refit_grid;
   }
   if ((e = hipGraphLaunch(sl.exec, stream)) != hipSuccess) return device_error(ctx, e, "graph launch");
   if ((e = hipEventRecord(sl.done, stream)) != hipSuccess) return device_error(ctx, e, "event record");

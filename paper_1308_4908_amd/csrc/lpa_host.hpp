@@ -107,6 +107,7 @@ struct BatchSlot {
   int64_t sig[5] = {0, 0, 0, 0, 0};  // source kind, block, grid, capacity, raw float DN
   int lds = 0;                    // dynamic LDS of the fit node (float2 elements)
   int refit_lds = 0;              // dynamic LDS of the refit node (bytes)
+  int refit_grid = 0;             // workgroups of the refit node
 };
 
 // Byte layout of a batch table of capacity cap.
@@ -190,12 +191,11 @@ lpa_status build_launch_fit(const lpa_rig* rig, const Resolved& R, const lpa_fra
 // (the serving scheduler charges a frame's whole footprint at admission).
 lpa_status alloc_async(lpa_ctx* ctx, size_t bytes, hipStream_t st, void** p, bool charge = true);
 void free_async(lpa_ctx* ctx, void* p, size_t bytes, hipStream_t st, bool charge = true);
-// Allocates a frame's pre-pass planes (stream-ordered) and, with `launch`,
-// enqueues the pre-pass of every sensor; batches leave `launch` off, their
-// graph fills the planes.
+// Allocates a frame's pre-pass planes (stream-ordered) and enqueues the
+// pre-pass of every sensor (batches carve their planes from one allocation
+// and their graph fills them).
 lpa_status run_prepass(lpa_rig* rig, const lpa_frame* f, bool to_f16, hipStream_t st, void** planes,
-                       size_t* plane_bytes, const void** srcs, int64_t* pitches, bool charge = true,
-                       bool launch = true);
+                       size_t* plane_bytes, const void** srcs, int64_t* pitches, bool charge = true);
 // Pre-computed-weight table of a launch (lpa_stencil.cpp): checks that every
 // sensor map and the output map are translations, then returns the rig's
 // cached device table for the launch's radii and windows, building it on

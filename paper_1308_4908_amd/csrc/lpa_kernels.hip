@@ -1112,9 +1112,10 @@ __global__ void __launch_bounds__(kRefitThreads) refit_kernel(const LaunchK K) {
                                   offs);
 }
 
-// Batch form: the batch's blocks, frame after frame, are numbered 0, 1, ...;
-// workgroup w takes blocks w, w + gridDim.x, ... (frames without refits have
-// no blocks).
+// Batch form: the batch's blocks, frame after frame, are numbered 0, 1, ...
+// (frames without refits have no blocks); one workgroup per block, as in
+// refit_kernel.  (A persistent loop over blocks costs the order-2 refit
+// about 85 more VGPRs, and with them half its occupancy.)
 template <typename RawT>
 __device__ __forceinline__ void refit_batch_frame(const LaunchK& K, int b, uint16_t* list, int* count, RawT* raw,
                                                   Region* regs, int* offs) {
@@ -1125,7 +1126,8 @@ __device__ __forceinline__ void refit_batch_frame(const LaunchK& K, int b, uint1
   }
 }
 
-// (all frames of a batch share the raw element type RawT)
+// (all frames of a batch share the raw element type RawT; the grid is the
+// batch's block count, or 1 if it has none)
 template <typename RawT>
 __global__ void __launch_bounds__(kRefitThreads) refit_batch_kernel(const BatchHeader* __restrict__ hdr,
                                                                     const LaunchK* __restrict__ frames,
@@ -1137,17 +1139,20 @@ __global__ void __launch_bounds__(kRefitThreads) refit_batch_kernel(const BatchH
   __shared__ Region regs[kMaxSensors];
   __shared__ int offs[kMaxSensors];
   const int n_frames = hdr->n_frames;
-  // the workgroup's slot: XCD-contiguous (workgroup i runs on XCD i mod 8),
+  // the workgroup's block: XCD-contiguous (workgroup i runs on XCD i mod 8),
   // so that neighbouring blocks share their halos in one L2
-  int64_t g = xcd_tile(blockIdx.x, gridDim.x), base = 0;
-  for (int f = 0; f < n_frames; ++f) {
+  const int64_t g = xcd_tile(blockIdx.x, gridDim.x);
+  int64_t base = 0;
+  int f = 0;
+  for (; f < n_frames; ++f) {
     const LaunchK& K = frames[f];
     if (!K.refit_map) continue;
     const int64_t nb = (int64_t)((K.out_w + K.refit_bw - 1) / K.refit_bw) * ((K.out_h + K.refit_bh - 1) / K.refit_bh);
-    for (; g < base + nb; g += gridDim.x)
-      refit_batch_frame<RawT>(K, (int)(g - base), list, count, reinterpret_cast<RawT*>(lds), regs, offs);
+    if (g < base + nb) break;
     base += nb;
   }
+  if (f >= n_frames) return;
+  refit_batch_frame<RawT>(frames[f], (int)(g - base), list, count, reinterpret_cast<RawT*>(lds), regs, offs);
 }
 
 // Pre-computed window weights: one tabulated sample of a stencil.  The entry
@@ -1795,10 +1800,26 @@ __global__ void __launch_bounds__(256) prepass_kernel(const SensorK S, const voi
 
 // The pre-pass of a whole batch (plane storage forms), one launch inside the
 // batch graph: workgroup row blockIdx.y is frame y / kMaxSensors, sensor
-// y % kMaxSensors of the batch table; its workgroups stride over that
-// sensor's rows, 256 lanes along a row.  Reads each frame's raw plane
-// (S.raw) and writes the plane the fit reads (S.src, allocated by the library
-// for this launch).
+// y % kMaxSensors of the batch table; its workgroups take bands of
+// kPreRows rows (band blockIdx.x, then every gridDim.x-th).  Reads each
+// frame's raw plane (S.raw) and writes the plane the fit reads (S.src,
+// allocated by the library for this launch).  Where both planes' rows are
+// 16-byte aligned, a lane converts 8 consecutive samples of every row of the
+// band, with all the band's loads issued before the first conversion (16-byte
+// loads and stores; the work is latency-bound with one sample per load).
+constexpr int kPreRows = 4;
+
+template <bool TO_F16>
+__device__ __forceinline__ void prepass_one(const SensorK& S, float dn, float4 c, char* prow, int x) {
+  if constexpr (TO_F16) {
+    const float norm_encode = 1.f / S.norm_decode;  // a power of two: exact
+    reinterpret_cast<__half*>(prow)[x] = (dn < c.w) ? __float2half_rn((dn - S.norm_offset) * norm_encode)
+                                                    : __ushort_as_half((unsigned short)0x7C00u);
+  } else {
+    reinterpret_cast<float2*>(prow)[x] = (S.calib != nullptr) ? decode_dn_cal(S, dn, c) : decode_dn(S, dn);
+  }
+}
+
 template <bool TO_F16>
 __global__ void __launch_bounds__(256) prepass_batch_kernel(const BatchHeader* __restrict__ hdr,
                                                             const LaunchK* __restrict__ frames) {
@@ -1809,20 +1830,76 @@ __global__ void __launch_bounds__(256) prepass_batch_kernel(const BatchHeader* _
   const SensorK& S = K.s[s];
   const bool raw_f32 = S.raw_f32 != 0;
   const bool cal = S.calib != nullptr;
-  const float norm_encode = 1.f / S.norm_decode;  // a power of two: exact
-  for (int y = blockIdx.x; y < S.height; y += gridDim.x) {
-    const char* rrow = static_cast<const char*>(S.raw) + (int64_t)y * S.raw_pitch;
-    char* prow = static_cast<char*>(const_cast<void*>(S.src)) + (int64_t)y * S.pitch;
-    for (int x = threadIdx.x; x < S.width; x += 256) {
-      const float dn = raw_f32 ? reinterpret_cast<const float*>(rrow)[x]
-                               : (float)reinterpret_cast<const uint16_t*>(rrow)[x];
-      const float4 c = cal ? S.calib[(int64_t)y * S.width + x] : make_float4(S.black, S.inv_ge, S.read_var, S.sat);
-      if constexpr (TO_F16) {
-        const __half h = (dn < c.w) ? __float2half_rn((dn - S.norm_offset) * norm_encode)
-                                    : __ushort_as_half((unsigned short)0x7C00u);
-        reinterpret_cast<__half*>(prow)[x] = h;
-      } else {
-        reinterpret_cast<float2*>(prow)[x] = cal ? decode_dn_cal(S, dn, c) : decode_dn(S, dn);
+  const float4 c0 = make_float4(S.black, S.inv_ge, S.read_var, S.sat);
+  const bool vec = ((reinterpret_cast<uintptr_t>(S.raw) | (uintptr_t)S.raw_pitch |
+                     reinterpret_cast<uintptr_t>(S.src) | (uintptr_t)S.pitch) & 15) == 0;
+  const int W = S.width, H = S.height;
+  const int w8 = vec ? (W & ~7) : 0;  // samples converted 8 at a time
+  for (int y0 = kPreRows * blockIdx.x; y0 < H; y0 += kPreRows * gridDim.x) {
+    const int nr = min(kPreRows, H - y0);
+    for (int x0 = 8 * threadIdx.x; x0 < w8; x0 += 8 * 256) {
+      float dn[kPreRows][8];
+#pragma unroll
+      for (int r = 0; r < kPreRows; ++r) {
+        if (r < nr) {
+          const char* rrow = static_cast<const char*>(S.raw) + (int64_t)(y0 + r) * S.raw_pitch;
+          if (raw_f32) {
+            const float4 a = reinterpret_cast<const float4*>(rrow)[x0 >> 2];
+            const float4 b = reinterpret_cast<const float4*>(rrow)[(x0 >> 2) + 1];
+            dn[r][0] = a.x; dn[r][1] = a.y; dn[r][2] = a.z; dn[r][3] = a.w;
+            dn[r][4] = b.x; dn[r][5] = b.y; dn[r][6] = b.z; dn[r][7] = b.w;
+          } else {
+            const uint4 q = reinterpret_cast<const uint4*>(rrow)[x0 >> 3];
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              dn[r][2 * k] = (float)(w[k] & 0xFFFFu);
+              dn[r][2 * k + 1] = (float)(w[k] >> 16);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kPreRows; ++r) {
+        if (r < nr) {
+          const int y = y0 + r;
+          char* prow = static_cast<char*>(const_cast<void*>(S.src)) + (int64_t)y * S.pitch;
+          float4 c[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) c[k] = cal ? S.calib[(int64_t)y * W + x0 + k] : c0;
+          if constexpr (TO_F16) {
+            const float norm_encode = 1.f / S.norm_decode;  // a power of two: exact
+            uint32_t w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const float d0 = dn[r][2 * k], d1 = dn[r][2 * k + 1];
+              const __half h0 = (d0 < c[2 * k].w) ? __float2half_rn((d0 - S.norm_offset) * norm_encode)
+                                                  : __ushort_as_half((unsigned short)0x7C00u);
+              const __half h1 = (d1 < c[2 * k + 1].w) ? __float2half_rn((d1 - S.norm_offset) * norm_encode)
+                                                      : __ushort_as_half((unsigned short)0x7C00u);
+              w[k] = (uint32_t)__half_as_ushort(h0) | ((uint32_t)__half_as_ushort(h1) << 16);
+            }
+            reinterpret_cast<uint4*>(prow)[x0 >> 3] = make_uint4(w[0], w[1], w[2], w[3]);
+          } else {
+            float2 v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = cal ? decode_dn_cal(S, dn[r][k], c[k]) : decode_dn(S, dn[r][k]);
+            float4* o = reinterpret_cast<float4*>(prow) + (x0 >> 1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[k] = make_float4(v[2 * k].x, v[2 * k].y, v[2 * k + 1].x, v[2 * k + 1].y);
+          }
+        }
+      }
+    }
+    // the samples past the last group of 8 (all of them where rows are not aligned)
+    for (int r = 0; r < nr; ++r) {
+      const int y = y0 + r;
+      const char* rrow = static_cast<const char*>(S.raw) + (int64_t)y * S.raw_pitch;
+      char* prow = static_cast<char*>(const_cast<void*>(S.src)) + (int64_t)y * S.pitch;
+      for (int x = w8 + threadIdx.x; x < W; x += 256) {
+        const float dn = raw_f32 ? reinterpret_cast<const float*>(rrow)[x]
+                                 : (float)reinterpret_cast<const uint16_t*>(rrow)[x];
+        prepass_one<TO_F16>(S, dn, cal ? S.calib[(int64_t)y * W + x] : c0, prow, x);
       }
     }
   }
@@ -2232,7 +2309,7 @@ extern "C" int lpa_k_batch_graph(hipGraph_t* out, hipGraphNode_t* fit_node, hipG
     hipKernelNodeParams q{};
     q.func = src_kind == SRC_PLANE_F16 ? reinterpret_cast<void*>(&prepass_batch_kernel<true>)
                                        : reinterpret_cast<void*>(&prepass_batch_kernel<false>);
-    q.gridDim = dim3(64, (unsigned)cap * kMaxSensors);
+    q.gridDim = dim3(128, (unsigned)cap * kMaxSensors);
     q.blockDim = dim3(256);
     q.sharedMemBytes = 0;
     q.kernelParams = pre_args;
