@@ -66,6 +66,8 @@ FLOP_PER_SOLVE = 294          # 6x6 equilibrated Cholesky + C0 + variance
 # sample-radius update w f and K w (2) and the 36 moment FMAs (72).
 FLOP_PER_SAMPLE_STENCIL = 5
 FLOP_PER_SAMPLE_SCALE_STENCIL = 74
+# A steered window's test d^T C d takes two more operations than |d|^2.
+FLOP_PER_SAMPLE_SCALE_STEER = FLOP_PER_SAMPLE_SCALE + 2
 
 # The paper's own timings (Sec. 8), for context only: order-0 LPA with one
 # fixed window, 4 sensors to a 2336 x 1752 output on a GeForce GTX 680, at
@@ -652,6 +654,19 @@ def main():
                  "accuracy": None}
         steer = torch.empty((params["out_h"], params["out_w"], 4), device="cuda")
         calpa.update(frame_counts(one_pass(pc, rig, dev, out, smap, steer=steer), n_px))
+        # the steered fit's algorithmic work: the ellipse d^T C d < r^2 holds
+        # pi r^2 / sqrt(det C) of a sensor's pixels, so samples and updates
+        # scale by the frame's mean 1 / sqrt(det C)
+        det = steer[..., 0].double() * steer[..., 2].double() - steer[..., 1].double() ** 2
+        area = float(torch.mean(torch.rsqrt(det)).item())
+        c_flop_px = (FLOP_PER_SAMPLE * samples_px * area + FLOP_PER_SAMPLE_SCALE_STEER * updates_px * area +
+                     FLOP_PER_SOLVE * 3 * len(RADII))
+        c_ms_k = kt_c.fit_ms / max(kt_c.n_fit, 1)
+        c_ach = c_flop_px * n_px / (c_ms_k * 1e-3) / 1e12
+        calpa["roofline"] = {"bound": "alu", "kernel": "fit_kernel_steer<order 2, ICI, raw uint16>",
+                             "achieved": round(c_ach, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(c_ach / PEAK_FP32_VECTOR_TFLOPS, 4), "flop_per_pixel": round(c_flop_px, 1),
+                             "mean_window_area_vs_isotropic": round(area, 4), "kernel_ms_per_launch": round(c_ms_k, 4)}
         pix = sample_pixels(params["out_w"], params["out_h"], 4096, 2200)
         c_steer = gather(torch, steer, pix)[:, :3].astype(np.float64)
         checks.append(Check(calpa, sensors, raws, pc, pix, gather(torch, out, pix), gather(torch, smap, pix),
