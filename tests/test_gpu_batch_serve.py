@@ -95,6 +95,56 @@ def test_batch_equals_alone_across_replays(torch_mod, storage):
     ctx.close()
 
 
+@pytest.mark.parametrize("storage", ["fp16", "fp32"])
+def test_batch_prepass_rows_unaligned_and_ragged(torch_mod, storage):
+    """The batch pre-pass converts 8 samples per lane with 16-byte loads where
+    both planes' rows are 16-byte aligned, and one at a time elsewhere and past
+    the last group of 8.  Frames of odd widths, raw rows contiguous (unaligned
+    pitch) or views into a wider buffer (aligned pitch, ragged tail), uint16
+    and float DN: each batched frame equals its per-frame result bit for bit
+    (the per-frame pre-pass converts one sample per lane)."""
+    torch = torch_mod
+    from paper_1308_4908_amd import Context, Rig
+    from synth import rig as R
+
+    ctx = Context(0)
+    specs = [(93, 61, 2, False), (77, 50, 3, True), (93, 61, 4, True), (61, 37, 2, False)]
+    for dt in (np.uint16, np.float32):
+        rigs, devs, params, refs = [], [], [], []
+        for k, (w, h, ns, padded) in enumerate(specs):
+            seed = 4700 + k
+            exps = [1.0, 1 / 8, 1 / 64, 1 / 4][:ns]
+            sensors = R.random_rig(ns, w, h, exps, 2.0, 0.3, seed, **configs.NOISE)
+            raws = configs.capture_all(EdgeScene(w, h, seed, n_lines=6), sensors, seed)
+            dev = []
+            for r in raws:
+                r = r.astype(dt)
+                if padded:  # a view into rows of 96 samples: aligned pitch, ragged tail
+                    buf = np.zeros((h, 96), dt)
+                    buf[:, :w] = r
+                    dev.append(torch.from_numpy(buf).cuda()[:, :w])
+                else:
+                    dev.append(torch.from_numpy(np.ascontiguousarray(r)).cuda())
+            p = configs.lpa_params(w, h, 1 + (k % 2), [1.0, 2.0, 3.0], storage=storage)
+            rig = Rig(ctx, sensors)
+            rigs.append(rig)
+            devs.append(dev)
+            params.append(p)
+            refs.append(alone(torch, ctx, rig, dev, p))
+        outs = [torch.full((p["out_h"], p["out_w"], 3), -3.0, device="cuda") for p in params]
+        maps = [torch.zeros((p["out_h"], p["out_w"], 3), dtype=torch.uint8, device="cuda") for p in params]
+        _say(f"[gpu] batch pre-pass storage={storage} raw {np.dtype(dt).name}")
+        ctx.reconstruct_batch(rigs, devs, params, outs, maps)
+        torch.cuda.synchronize()
+        for i in range(len(specs)):
+            assert np.array_equal(outs[i].cpu().numpy(), refs[i][0], equal_nan=True), f"frame {i} {np.dtype(dt).name}"
+            assert np.array_equal(maps[i].cpu().numpy(), refs[i][1]), f"frame {i} map"
+        for rig in rigs:
+            rig.close()
+    torch.cuda.synchronize()
+    ctx.close()
+
+
 def test_batch_graph_reused_across_lds_sizes(torch_mod):
     """Consecutive batches of frames that need different LDS sizes (2- and
     4-sensor frames) replay each slot's graph with its kernel nodes updated:
