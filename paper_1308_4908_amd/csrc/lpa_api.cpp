@@ -695,7 +695,9 @@ void timing_clear_locked(lpa_ctx* ctx) {
 }
 
 // Register budget of the pre-computed-weight kernel (waves per SIMD; 0 = 3).
-constexpr int kStencilOccupancy = 0;
+// Its entry loop waits on scalar loads and the LDS reads they address: 4
+// waves hide more of that latency than the few spilled registers cost.
+constexpr int kStencilOccupancy = 4;
 
 lpa_status reconstruct_impl(lpa_rig* rig, const lpa_frame* frame, const lpa_params* params,
                             const lpa_output* out, void* stream, bool plain) {
