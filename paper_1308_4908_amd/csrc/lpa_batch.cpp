@@ -229,13 +229,18 @@ lpa_status launch_table(lpa_ctx* ctx, const std::vector<LaunchK>& ks, int src_ki
   const auto* d_frames = reinterpret_cast<const LaunchK*>(d + L.frames_off);
   const auto* d_first = reinterpret_cast<const int64_t*>(d + L.first_off);
   auto* d_queue = reinterpret_cast<int32_t*>(d + L.queue_off);
-  // the refit takes one workgroup per output block of the frames it covers
-  int64_t refit_blocks = 0;
+  // the refit takes one workgroup per output block of the frames that have
+  // refits, each of the 8 XCDs an eighth of every frame's blocks: the grid is
+  // 8 x the largest per-XCD count (refit_batch_kernel)
+  int64_t per_xcd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (const LaunchK& K : ks)
-    if (K.refit_map)
-      refit_blocks += (int64_t)((K.out_w + K.refit_bw - 1) / K.refit_bw) * ((K.out_h + K.refit_bh - 1) / K.refit_bh);
+    if (K.refit_map) {
+      const int64_t nb = (int64_t)((K.out_w + K.refit_bw - 1) / K.refit_bw) * ((K.out_h + K.refit_bh - 1) / K.refit_bh);
+      for (int x = 0; x < 8; ++x) per_xcd[x] += nb * (x + 1) / 8 - nb * x / 8;
+    }
+  const int64_t refit_blocks = 8 * std::max<int64_t>(*std::max_element(per_xcd, per_xcd + 8), 1);
   if (refit_blocks > (int64_t)INT32_MAX) return set_error(LPA_ERR_UNSUPPORTED, "batch exceeds 2^31 refit blocks");
-  const int refit_grid = (int)std::max<int64_t>(refit_blocks, 1);
+  const int refit_grid = (int)refit_blocks;
   bool rebuild = !sl.exec || std::memcmp(sig, sl.sig, sizeof(sig)) != 0;
   if (!rebuild && (sl.lds != lds || sl.refit_lds != refit_lds || sl.refit_grid != refit_grid)) {
     // another LDS size or refit grid: update the two nodes in place; a

@@ -1130,8 +1130,14 @@ __device__ __forceinline__ void refit_batch_frame(const LaunchK& K, int b, uint1
   }
 }
 
-// (all frames of a batch share the raw element type RawT; the grid is the
-// batch's block count, or 1 if it has none)
+// (all frames of a batch share the raw element type RawT.)  Workgroup i runs
+// on XCD x = i mod 8 (round-robin dispatch) as that XCD's j = i / 8-th
+// workgroup.  Each XCD takes the x-th eighth of every frame's blocks, frame
+// after frame: neighbouring blocks share their halos in its L2, and every XCD
+// gets a share of every frame (frames differ widely in how many outputs they
+// mark; contiguous ranges of the batch would leave some XCDs idle).  The grid
+// is 8 x the largest per-XCD block count; workgroups past their XCD's count
+// return at once.
 template <typename RawT>
 __global__ void __launch_bounds__(kRefitThreads) refit_batch_kernel(const BatchHeader* __restrict__ hdr,
                                                                     const LaunchK* __restrict__ frames,
@@ -1143,20 +1149,23 @@ __global__ void __launch_bounds__(kRefitThreads) refit_batch_kernel(const BatchH
   __shared__ Region regs[kMaxSensors];
   __shared__ int offs[kMaxSensors];
   const int n_frames = hdr->n_frames;
-  // the workgroup's block: XCD-contiguous (workgroup i runs on XCD i mod 8),
-  // so that neighbouring blocks share their halos in one L2
-  const int64_t g = xcd_tile(blockIdx.x, gridDim.x);
-  int64_t base = 0;
+  const int x = (int)(blockIdx.x % kXcds);
+  const int64_t j = blockIdx.x / kXcds;
+  int64_t base = 0, lo = 0;
   int f = 0;
   for (; f < n_frames; ++f) {
     const LaunchK& K = frames[f];
     if (!K.refit_map) continue;
     const int64_t nb = (int64_t)((K.out_w + K.refit_bw - 1) / K.refit_bw) * ((K.out_h + K.refit_bh - 1) / K.refit_bh);
-    if (g < base + nb) break;
-    base += nb;
+    const int64_t a = nb * x / kXcds, b = nb * (x + 1) / kXcds;  // this XCD's slice
+    if (j < base + (b - a)) {
+      lo = a;
+      break;
+    }
+    base += b - a;
   }
   if (f >= n_frames) return;
-  refit_batch_frame<RawT>(frames[f], (int)(g - base), list, count, reinterpret_cast<RawT*>(lds), regs, offs);
+  refit_batch_frame<RawT>(frames[f], (int)(lo + (j - base)), list, count, reinterpret_cast<RawT*>(lds), regs, offs);
 }
 
 // Pre-computed window weights: one tabulated sample of a stencil.  The entry
