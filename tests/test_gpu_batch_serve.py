@@ -145,6 +145,55 @@ def test_batch_prepass_rows_unaligned_and_ragged(torch_mod, storage):
     ctx.close()
 
 
+def test_batch_refit_blocks_sliced_over_xcds(torch_mod):
+    """The batch refit gives each of the 8 XCDs an eighth of every frame's
+    32x32 output blocks (uneven slices: 12 to 80 blocks per frame, frames with
+    and without refits).  Every batched frame equals its per-frame result bit
+    for bit, and the FP64-refit counts match, with hundreds of refit outputs
+    per frame."""
+    torch = torch_mod
+    from paper_1308_4908_amd import Context, Rig
+    from synth import rig as R
+
+    ctx = Context(0)
+    specs = [(320, 200, 4), (256, 256, 3), (200, 320, 2), (130, 90, 3), (300, 140, 4)]
+    rigs, devs, params, refs, counts = [], [], [], [], []
+    for k, (w, h, ns) in enumerate(specs):
+        seed = 4800 + k
+        sensors = R.random_rig(ns, w, h, [1.0, 1 / 16, 1 / 128, 1 / 4][:ns], 2.0, 0.3, seed, **configs.NOISE)
+        raws = configs.capture_all(EdgeScene(w, h, seed, n_lines=8), sensors, seed)
+        dev = [torch.from_numpy(r).cuda() for r in raws]
+        p = configs.lpa_params(w, h, 2 - (k % 2), [1.0, 2.0, 3.0, 4.0])
+        if k == 3:
+            p = dict(p, value_tol=-1.0)  # no accuracy target: no refit blocks for this frame
+        rig = Rig(ctx, sensors)
+        st = torch.zeros(2, dtype=torch.int64, device="cuda")
+        out = torch.empty((h, w, 3), device="cuda")
+        smap = torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")
+        rig.reconstruct(dev, p, out, smap, stats=st)
+        torch.cuda.synchronize()
+        rigs.append(rig)
+        devs.append(dev)
+        params.append(p)
+        refs.append((out.cpu().numpy(), smap.cpu().numpy()))
+        counts.append(st.cpu().numpy())
+    assert sum(int(c[0]) for c in counts) > 1000
+    outs = [torch.full((p["out_h"], p["out_w"], 3), -5.0, device="cuda") for p in params]
+    maps = [torch.zeros((p["out_h"], p["out_w"], 3), dtype=torch.uint8, device="cuda") for p in params]
+    stats = [torch.full((2,), -1, dtype=torch.int64, device="cuda") for _ in params]
+    _say(f"[gpu] batch refit over XCD slices, fp64 counts {[int(c[0]) for c in counts]}")
+    ctx.reconstruct_batch(rigs, devs, params, outs, maps, stats=stats)
+    torch.cuda.synchronize()
+    for i in range(len(specs)):
+        assert np.array_equal(outs[i].cpu().numpy(), refs[i][0], equal_nan=True), f"frame {i}"
+        assert np.array_equal(maps[i].cpu().numpy(), refs[i][1]), f"frame {i} map"
+        assert np.array_equal(stats[i].cpu().numpy(), counts[i]), f"frame {i} counts"
+    for rig in rigs:
+        rig.close()
+    torch.cuda.synchronize()
+    ctx.close()
+
+
 def test_batch_graph_reused_across_lds_sizes(torch_mod):
     """Consecutive batches of frames that need different LDS sizes (2- and
     4-sensor frames) replay each slot's graph with its kernel nodes updated:
