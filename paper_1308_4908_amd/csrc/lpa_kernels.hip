@@ -1103,9 +1103,11 @@ __device__ __forceinline__ void refit_block(const LaunchK& K, int b, uint16_t* l
 
 // One workgroup per output block; dynamic LDS: the raw samples of the block's
 // footprints (K.refit_lds elements of RawT: uint16 frames as uint16, float DN
-// as float).
+// as float).  Compiled for 4 waves per SIMD: the FP64 walks are latency-bound,
+// and the extra waves outweigh the registers spilled to reach 128 VGPRs.
 template <int ORDER, bool STEER, typename RawT>
-__global__ void __launch_bounds__(kRefitThreads) refit_kernel(const LaunchK K) {
+__global__ void __launch_bounds__(kRefitThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+refit_kernel(const LaunchK K) {
   extern __shared__ float2 lds[];
   __shared__ uint16_t list[kRefitMaxOut];
   __shared__ int count[kRefitClasses + 1];
