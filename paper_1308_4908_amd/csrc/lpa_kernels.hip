@@ -1132,7 +1132,8 @@ __device__ __forceinline__ void refit_batch_frame(const LaunchK& K, int b, uint1
   }
 }
 
-// (all frames of a batch share the raw element type RawT.)  Workgroup i runs
+// (all frames of a batch share the raw element type RawT; 4 waves per SIMD,
+// as refit_kernel.)  Workgroup i runs
 // on XCD x = i mod 8 (round-robin dispatch) as that XCD's j = i / 8-th
 // workgroup.  Each XCD takes the x-th eighth of every frame's blocks, frame
 // after frame: neighbouring blocks share their halos in its L2, and every XCD
@@ -1141,7 +1142,8 @@ __device__ __forceinline__ void refit_batch_frame(const LaunchK& K, int b, uint1
 // is 8 x the largest per-XCD block count; workgroups past their XCD's count
 // return at once.
 template <typename RawT>
-__global__ void __launch_bounds__(kRefitThreads) refit_batch_kernel(const BatchHeader* __restrict__ hdr,
+__global__ void __launch_bounds__(kRefitThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+refit_batch_kernel(const BatchHeader* __restrict__ hdr,
                                                                     const LaunchK* __restrict__ frames,
                                                                     const int64_t* __restrict__ first_tile) {
   (void)first_tile;
