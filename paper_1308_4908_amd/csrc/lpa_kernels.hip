@@ -658,6 +658,31 @@ __device__ __forceinline__ void stage_tile(const LaunchK& K, int u0, int v0, flo
   }
 }
 
+// Raw form of the staging (16-bit raw frames without calibration frames):
+// each sample stays a 16-bit DN in LDS, a quarter of the decoded float2, and
+// is decoded where a walk reads it.  Samples outside the sensor are staged as
+// 0xFFFF, which no sensor's saturation (at most 65535 DN for 16-bit data)
+// admits: they decode as masked, as load_sample makes them.
+__device__ __forceinline__ void stage_tile_raw16(const LaunchK& K, int u0, int v0, uint16_t* lds16, Region* regs,
+                                                 int tid, int nthreads) {
+  for (int s = 0; s < K.n_sensors; ++s) {
+    const SensorK& S = K.s[s];
+    const Region r = tile_region(K, S, u0, v0);
+    regs[s] = r;
+    uint16_t* dst = lds16 + S.lds_off;
+    const int total = r.w * r.h;
+    for (int e = tid; e < total; e += nthreads) {
+      const int row = e / r.w;
+      const int col = e - row * r.w;
+      const int x = r.x0 + col, y = r.y0 + row;
+      uint16_t v = 0xFFFFu;
+      if (x >= 0 && y >= 0 && x < S.width && y < S.height)
+        v = reinterpret_cast<const uint16_t*>(static_cast<const char*>(S.src) + (int64_t)y * S.pitch)[x];
+      dst[e] = v;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Per-pixel fit of one tile.  All loop bounds are uniform across the wave.
 // ---------------------------------------------------------------------------
@@ -683,25 +708,24 @@ constexpr float kPivotCertifiesN = 1e-3f;
 // accumulator where they merge).
 constexpr int kBlk = 5;
 
-template <class Fn>
-__device__ __forceinline__ void walk_box(const float2* p0, int row_step, int nx, int ny, float c0x, float c0y,
+template <typename T, class Fn>
+__device__ __forceinline__ void walk_box(const T* p0, int row_step, int nx, int ny, float c0x, float c0y,
                                          float sax, float say, float sbx, float sby, Fn& fn) {
   for (int jb = 0; jb < ny; jb += kBlk) {
     for (int ib = 0; ib < nx; ib += kBlk) {
       const int mx = nx - ib, my = ny - jb;
-      const float2* pb = p0 + jb * row_step + 2 * ib;
+      const T* pb = p0 + jb * row_step + 2 * ib;
       float rx = __builtin_fmaf((float)ib, sax, __builtin_fmaf((float)jb, sbx, c0x));
       float ry = __builtin_fmaf((float)ib, say, __builtin_fmaf((float)jb, sby, c0y));
 #pragma unroll
       for (int jj = 0; jj < kBlk; ++jj) {
         if (jj < my) {
-          const float2* prow = pb + jj * row_step;
+          const T* prow = pb + jj * row_step;
           float dx = rx, dy = ry;
 #pragma unroll
           for (int ii = 0; ii < kBlk; ++ii) {
             if (ii < mx) {
-              const float2 sm = prow[2 * ii];
-              fn(dx, dy, sm.x, sm.y);
+              fn(dx, dy, prow[2 * ii]);
               dx += sax;
               dy += say;
             }
@@ -733,7 +757,7 @@ __device__ __forceinline__ float wave_max(float x) {
 // box holds the disk of the radius; for steered windows, the wave's ellipses
 // (half-widths from SteerBox, at most the box of the largest stretch, which
 // the staged tile region covers).
-template <bool STEER, class Fn>
+template <bool STEER, bool RAW16 = false, class Fn>
 __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds, const Region* regs,
                                              double Xj, double Yj, int c, int cls, int m, const SteerBox& sb,
                                              Fn&& fn) {
@@ -763,7 +787,6 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
     // step between sub-lattice points (+2 px in x or y), scaled
     const float sax = (float)(2.0 * S.fwd[0] * cs), say = (float)(2.0 * S.fwd[3] * cs);
     const float sbx = (float)(2.0 * S.fwd[1] * cs), sby = (float)(2.0 * S.fwd[4] * cs);
-    const float2* plane = lds + S.lds_off;
     const int row_step = 2 * R.w;
     const int nsub = S.sub_n[c];
     for (int q = 0; q < nsub; ++q) {
@@ -778,9 +801,19 @@ __device__ __forceinline__ void walk_support(const LaunchK& K, const float2* lds
       const float c0y = (float)((Yb - Yj) * cs);
       // row index times pitch: both are below 2^24 (the box lies inside the
       // staged region), so the full-rate 24-bit multiply is exact
-      const float2* p0 = plane + __mul24(yb - R.y0, R.w) + (xb - R.x0);
-      auto fs = [&](float dx, float dy, float f, float iv) { fn(dx, dy, f, iv, s); };
-      walk_box(p0, row_step, nx, ny, c0x, c0y, sax, say, sbx, sby, fs);
+      const int at = S.lds_off + __mul24(yb - R.y0, R.w) + (xb - R.x0);
+      if constexpr (RAW16) {
+        const uint16_t* p0 = reinterpret_cast<const uint16_t*>(lds) + at;
+        auto fs = [&](float dx, float dy, uint16_t dn) {
+          const float2 d = decode_dn(S, (float)dn);
+          fn(dx, dy, d.x, d.y, s);
+        };
+        walk_box(p0, row_step, nx, ny, c0x, c0y, sax, say, sbx, sby, fs);
+      } else {
+        const float2* p0 = lds + at;
+        auto fs = [&](float dx, float dy, float2 sm) { fn(dx, dy, sm.x, sm.y, s); };
+        walk_box(p0, row_step, nx, ny, c0x, c0y, sax, say, sbx, sby, fs);
+      }
     }
   }
 }
@@ -1229,7 +1262,7 @@ __device__ __forceinline__ void walk_stencil(const LaunchK& K, const float2* lds
 
 // cnt64 / cnt_nan count this lane's outputs marked for the FP64 refit and
 // those with no valid fit.
-template <int ORDER, bool ICI, bool STEER, bool STENCIL = false, bool TEMP = false>
+template <int ORDER, bool ICI, bool STEER, bool STENCIL = false, bool TEMP = false, bool RAW16 = false>
 __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, const Region* regs,
                                           int u, int v, bool active, int& cnt64, int& cnt_nan) {
   const double Xj = K.out_affine[0] * u + K.out_affine[1] * v + K.out_affine[2];
@@ -1288,13 +1321,13 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
                    ? 1
                    : 0;
         };
-        walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, accumulate);
+        walk_support<STEER, RAW16>(K, lds, regs, Xj, Yj, c, cls, m, sb, accumulate);
         n_first = n;
       } else {
         auto accumulate = [&](float dx, float dy, float f, float iv, int s) {
           acc_sample<ORDER, ICI, STEER, TEMP>(a, dx, dy, f, iv, eedge, reach2, sc, TEMP ? K.s[s].kt[m] : 1.f);
         };
-        walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, accumulate);
+        walk_support<STEER, RAW16>(K, lds, regs, Xj, Yj, c, cls, m, sb, accumulate);
       }
 
       // Once every lane of the wave has a valid top-order fit at some radius,
@@ -1358,7 +1391,7 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
               acc64_sample<ORDER, false>(a64, dx, dy, 0.f, w, hi);
             }
           };
-          walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, second);
+          walk_support<STEER, RAW16>(K, lds, regs, Xj, Yj, c, cls, m, sb, second);
           Fit64<ORDER> r64;
           if (hi) solve64<ORDER, ORDER, false>(a64, dbl, r64);
           else solve64<ORDER, 1, false>(a64, dbl, r64);  // only order-1 fits to redo
@@ -1404,7 +1437,7 @@ __device__ __forceinline__ void fit_pixel(const LaunchK& K, const float2* lds, c
                 }
               }
             };
-            walk_support<STEER>(K, lds, regs, Xj, Yj, c, cls, m, sb, third);
+            walk_support<STEER, RAW16>(K, lds, regs, Xj, Yj, c, cls, m, sb, third);
 #pragma unroll
             for (int o = 1; o <= ORDER; ++o) {
               if (redo[o]) {
@@ -1467,7 +1500,8 @@ struct TileShared {
   uint32_t stat[2];  // the tile's FP64-valued and no-data outputs
 };
 
-template <int ORDER, bool ICI, int SRC, bool STEER = false, bool STENCIL = false, bool TEMP = false>
+template <int ORDER, bool ICI, int SRC, bool STEER = false, bool STENCIL = false, bool TEMP = false,
+          bool RAW16 = false>
 __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2* lds, TileShared& sh) {
   const int tx = tile % K.tiles_x;
   const int ty = tile / K.tiles_x;
@@ -1475,7 +1509,8 @@ __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2*
   const int tid = threadIdx.x;
   const int nthreads = K.tile_w * K.tile_h;
   if (tid < 2) sh.stat[tid] = 0u;
-  stage_tile<SRC, STENCIL>(K, u0, v0, lds, sh.regs, tid, nthreads);
+  if constexpr (RAW16) stage_tile_raw16(K, u0, v0, reinterpret_cast<uint16_t*>(lds), sh.regs, tid, nthreads);
+  else stage_tile<SRC, STENCIL>(K, u0, v0, lds, sh.regs, tid, nthreads);
   __syncthreads();
   int du, dv;
   lane_pixel(tid, K.tile_w, K.tile_h, &du, &dv);
@@ -1483,7 +1518,7 @@ __device__ __forceinline__ void process_tile(const LaunchK& K, int tile, float2*
   const bool active = (u < K.out_w) && (v < K.out_h);
   // inactive lanes of a ragged tile compute at their nominal pixel (staged)
   int cnt64 = 0, cnt_nan = 0;
-  fit_pixel<ORDER, ICI, STEER, STENCIL, TEMP>(K, lds, sh.regs, u, v, active, cnt64, cnt_nan);
+  fit_pixel<ORDER, ICI, STEER, STENCIL, TEMP, RAW16>(K, lds, sh.regs, u, v, active, cnt64, cnt_nan);
   if (K.tile_stats) {
     if (cnt64) atomicAdd(&sh.stat[0], (uint32_t)cnt64);
     if (cnt_nan) atomicAdd(&sh.stat[1], (uint32_t)cnt_nan);
@@ -1524,6 +1559,17 @@ fit_kernel_temporal(const LaunchK K) {
   extern __shared__ float2 lds[];
   __shared__ TileShared sh;
   process_tile<ORDER, ICI, SRC, false, false, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, sh);
+}
+
+// The same with the tile staged as raw 16-bit DN (frames of 16-bit raw
+// without calibration frames): a quarter of the LDS, and with it more
+// workgroups per CU for the many staged sensors of a temporal support.
+template <int ORDER, bool ICI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+fit_kernel_temporal_raw16(const LaunchK K) {
+  extern __shared__ float2 lds[];
+  __shared__ TileShared sh;
+  process_tile<ORDER, ICI, SRC_RAW_U16, false, false, true, true>(K, xcd_tile(blockIdx.x, gridDim.x), lds, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -2092,6 +2138,15 @@ template <int ORDER, bool ICI>
 int launch_temporal_src(const LaunchK& K, hipStream_t st) {
   const dim3 grid(K.tiles_x * K.tiles_y), block(K.tile_w * K.tile_h);
   const size_t lds = (size_t)K.lds_floats2 * sizeof(float2);
+  // the raw staging needs every sensor to mask 0xFFFF (no calibration
+  // frames, saturation at most 65535 DN)
+  bool raw16 = K.src_kind == SRC_RAW_U16;
+  for (int s = 0; s < K.n_sensors; ++s) raw16 = raw16 && K.s[s].calib == nullptr && K.s[s].sat <= 65535.f;
+  if (raw16) {
+    const size_t lds16 = ((size_t)K.lds_floats2 * sizeof(uint16_t) + 15) / 16 * 16;
+    fit_kernel_temporal_raw16<ORDER, ICI><<<grid, block, lds16, st>>>(K);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+  }
   switch (K.src_kind) {
     case SRC_RAW_U16: fit_kernel_temporal<ORDER, ICI, SRC_RAW_U16><<<grid, block, lds, st>>>(K); break;
     case SRC_RAW_F32: fit_kernel_temporal<ORDER, ICI, SRC_RAW_F32><<<grid, block, lds, st>>>(K); break;
