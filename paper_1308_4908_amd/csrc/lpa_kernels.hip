@@ -1563,9 +1563,10 @@ fit_kernel_temporal(const LaunchK K) {
 
 // The same with the tile staged as raw 16-bit DN (frames of 16-bit raw
 // without calibration frames): a quarter of the LDS, and with it more
-// workgroups per CU for the many staged sensors of a temporal support.
+// workgroups per CU for the many staged sensors of a temporal support; then
+// registers bound the occupancy, and 4 waves per SIMD (a few spilled) beat 3.
 template <int ORDER, bool ICI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 fit_kernel_temporal_raw16(const LaunchK K) {
   extern __shared__ float2 lds[];
   __shared__ TileShared sh;
