@@ -1055,7 +1055,7 @@ __device__ __forceinline__ Region block_region(const LaunchK& K, const SensorK& 
 // CLOSE: end with a workgroup barrier.  Without one, waves without an output
 // end early and free their registers for other workgroups' waves; the batch
 // kernel keeps it (without it the compiler's schedule of the three inlined
-// orders needs 178 VGPRs instead of 156, one wave per SIMD fewer).
+// orders spills 224 bytes per lane at its 4-wave budget instead of 136).
 template <int ORDER, bool STEER, typename RawT, bool CLOSE = false>
 __device__ __forceinline__ void refit_block(const LaunchK& K, int b, uint16_t* list, int* count, RawT* raw,
                                             Region* regs, int* offs) {
